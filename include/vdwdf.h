@@ -1,0 +1,235 @@
+/*
+ * vdwdf.h -- C ABI of libvdwdf.so, the MI355X (gfx950) implementation of the
+ * vdW-DF nonlocal correlation energy and its potential.
+ *
+ * The method is the one of Lazic et al., "JuNoLo - Julich Non Local code for
+ * parallel calculation of vdW-DF nonlocal density functional theory"
+ * (arXiv:0810.2273):
+ *   - Sec. 2, Eq. (1): E_c^nl = 1/2 int int n(r) phi(r, r') n(r') d^3r d^3r';
+ *     the kernel depends on D >= 0 and |delta| < 1 and is the double integral
+ *     of Dion et al. (their Eq. 14), with their large-D asymptote (Eq. 17).
+ *   - Sec. 2, Eq. (2): on the density grid the integral is the double sum
+ *     E = 1/2 sum_i sum_j n_i phi_ij n_j (times dV^2, the volume elements).
+ *   - Sec. 3: the gradient of n by finite differences (perpendicular axes),
+ *     a density cut-off below which points are dropped, the sum over the
+ *     0th cell, then over periodic repetitions of it.
+ *
+ * Conventions for every entry point:
+ *   - Units are Hartree atomic units (bohr, Hartree, electrons/bohr^3).
+ *   - Grid arrays are FP64, x fastest: index = ix + nx (iy + ny iz).
+ *   - Pointers named *_d are DEVICE pointers (HIP global memory on the
+ *     current device); E_out is HOST memory.  The caller owns every buffer;
+ *     the library allocates nothing on these paths.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Work is enqueued asynchronously on it; the entry points that
+ *     write E_out synchronise that stream before returning.
+ *   - Every function returns VDW_OK (0) or a negative status; inputs are
+ *     validated on the host before anything is launched, and a failed call
+ *     leaves output buffers unspecified.  vdw_last_error() returns a
+ *     thread-local message describing the last failure.
+ *   - Calls on one stream are ordered; concurrent calls on different
+ *     streams must use different workspaces.
+ */
+#ifndef VDWDF_H
+#define VDWDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    VDW_OK = 0,
+    VDW_EINVAL = -1,        /* bad argument: null pointer, size, parameter range  */
+    VDW_ENOMEM = -2,        /* device allocation failed (table builder scratch)   */
+    VDW_EHIP = -3,          /* a HIP runtime call failed                          */
+    VDW_EUNSUPPORTED = -4,  /* valid but not implemented (skew cell with FD grad) */
+    VDW_EWORKSPACE = -5,    /* workspace smaller than enl_workspace_size()        */
+    VDW_ENONFINITE = -6     /* NaN or Inf found in the density                    */
+};
+
+enum { VDW_FP64 = 0, VDW_FP32C = 1 };
+
+/* Equidistant grid (Sec. 2).  cell[a] is the a-th cell vector (bohr); grid
+ * point (i, j, k) sits at i cell[0]/n[0] + j cell[1]/n[1] + k cell[2]/n[2].
+ * Only orthorhombic cells (cell[a][b] = 0 for a != b) are supported, because
+ * the finite-difference gradient is defined for perpendicular axes (Sec. 3);
+ * other cells give VDW_EUNSUPPORTED.  periodic[a] = 1 marks a periodic axis
+ * (the input's perx/pery/perz, App. A).  Every n[a] must be >= 3. */
+typedef struct {
+    int32_t n[3];
+    double  cell[3][3];
+    int32_t periodic[3];
+} vdw_grid;
+
+/* The kernel table (Sec. 2; node counts and limits are free parameters,
+ * Sec. 7).  Nodes D_k = k D_max/(n_D-1), sigma_l = l/(n_sigma-1) with
+ * sigma = delta^2; row-major phi[k * n_sigma + l].  The quadrature rule that
+ * fills it (the same rule the test oracle implements):
+ *   phi(d1,d2) = 2/pi^2 sum_i sum_j w_i w_j a_i^2 a_j^2 W(a_i,a_j)
+ *                T(nu(a_i), nu(a_j), nu'(a_i), nu'(a_j)),
+ *   d1 = D(1+delta), d2 = D(1-delta); nodes: gl_points Gauss-Legendre points
+ *   on each panel [0, w 2^-K], [w 2^-(j+1), w 2^-j] (j = K-1..0), then
+ *   [t w, (t+1) w] up to A, with w = pi/2, K = graded_levels, and A the
+ *   smallest odd multiple of w with A >= max(A0, kappa max(d1, d2)).
+ * Row 0 (D = 0, where phi diverges like -ln D) is the linear extrapolation
+ * 2 phi(D_1) - phi(D_2).  Defaults: gl_points 8, graded_levels 12,
+ * kappa 4, A0 64. */
+typedef struct {
+    int32_t n_D;
+    int32_t n_sigma;
+    double  D_max;
+    int32_t gl_points;      /* 2..32 */
+    int32_t graded_levels;  /* 0..40 */
+    double  kappa;          /* > 0   */
+    double  A0;             /* > 0   */
+} vdw_table_params;
+
+/* Options of the energy / potential evaluation. */
+typedef struct {
+    double  n_cut;          /* points with n < n_cut are dropped (Sec. 3); > 0    */
+    double  r_cut;          /* pair distance cut (bohr) applied to every (i,j,L);
+                               <= 0: none                                          */
+    int32_t image_max[3];   /* images |m_a| <= image_max[a] on periodic axes      */
+    int32_t precision;      /* VDW_FP64 or VDW_FP32C (FP32 pair terms with
+                               compensated FP32 runs carried in FP64)             */
+    int32_t self_term;      /* 1: add the on-site term E_self (below); 0: omit     */
+    int32_t table_lds_rows; /* rows of the table kept in LDS; -1: as many as fit  */
+    int32_t block_threads;  /* pair-kernel workgroup size 256/512/1024; 0: auto   */
+    int32_t j_chunks;       /* split of the j range per i-block (1..64); 0: auto  */
+    int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
+    int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only)     */
+} vdw_opts;
+
+/* Thread-local description of the last error (never NULL). */
+const char *vdw_last_error(void);
+
+/* Library version string. */
+const char *vdw_version(void);
+
+/* ---------------------------------------------------------------------
+ * build_phi_table -- fill the kernel table on the device (Sec. 2, the
+ * double integral of Dion et al.), in FP64.
+ *   phi_d: device, n_D * n_sigma doubles (written).
+ *   phi_f: device, n_D * n_sigma floats, or NULL (FP32 copy for the
+ *          VDW_FP32C pair kernel).
+ * Allocates a small device scratch for the quadrature nodes (freed before
+ * return) and synchronises `stream`.
+ * Errors: VDW_EINVAL (null phi_d, n_D < 3, n_sigma < 2, D_max <= 0,
+ * quadrature parameters out of range), VDW_ENOMEM, VDW_EHIP.
+ * ------------------------------------------------------------------- */
+int build_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, void *stream);
+
+/* ---------------------------------------------------------------------
+ * compute_q0 -- density gradient and q0 on every grid point (Sec. 3: FD
+ * gradient on perpendicular axes; q0 of Dion et al. from the LDA exchange
+ * and Perdew-Wang 1992 correlation plus the gradient term):
+ *   grad_a n: second-order central differences, periodic wrap on periodic
+ *             axes, second-order one-sided differences at the faces of
+ *             non-periodic axes;
+ *   q0 = k_F - (4 pi/3) eps_c^PW92(r_s) - (Z_ab/36) |grad n|^2 / (k_F n^2),
+ *        Z_ab = -0.8491, where n >= n_cut; 0 elsewhere.
+ *   n_d:     device, G doubles (read).
+ *   grad_d:  device, 3G doubles (planes d/dx, d/dy, d/dz), or NULL.
+ *   q0_d:    device, G doubles (written).
+ *   dq_dn_d: device, G doubles, or NULL: dq0/dn at fixed |grad n|^2.
+ *   dq_dg_d: device, G doubles, or NULL: dq0/d(|grad n|^2).
+ * Errors: VDW_EINVAL (null pointers, n_cut <= 0, n[a] < 3),
+ * VDW_EUNSUPPORTED (non-orthorhombic cell), VDW_EHIP.
+ * ------------------------------------------------------------------- */
+int compute_q0(const vdw_grid *grid, double n_cut, const double *n_d, double *grad_d, double *q0_d,
+               double *dq_dn_d, double *dq_dg_d, void *stream);
+
+/* Bytes of device workspace enl_energy / enl_potential need for this grid
+ * and these options (an upper bound that holds for any density). */
+size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, const vdw_opts *opts);
+
+/* ---------------------------------------------------------------------
+ * enl_energy -- E_c^nl of Eq. (2) over the retained points S = {n >= n_cut}
+ * (Sec. 3), with phi~ the table interpolant (bilinear in (D, sigma)) for
+ * D < D_max and -C/(d1^2 d2^2 (d1^2 + d2^2)), C = 12 (4 pi/9)^3, beyond:
+ *   E_pair0 = 1/2 dV^2 sum_{i != j in S} n_i n_j phi~(q_i, q_j, |r_i - r_j|)
+ *   E_pairL = 1/2 dV^2 sum_{i, j in S} sum_{L != 0} n_i n_j phi~(.., |r_i - r_j - L|)
+ *   E_self  = 1/2 dV^2 sum_{i in S} n_i^2 phi~(q_i rho_s, 0),
+ *             rho_s = (3 dV / 4 pi)^(1/3) e^(-1/3)     (if opts->self_term)
+ * L runs over the images selected by opts->image_max on periodic axes
+ * (Sec. 3, periodic problems), and every (i, j, L) with a distance above
+ * opts->r_cut (if > 0) is dropped.  dV = hx hy hz.
+ *   n_d, q0_d: device, G doubles (q0 from compute_q0).
+ *   phi_d:     device FP64 table (always required: the on-site term and the
+ *              VDW_FP64 pair kernel read it).
+ *   phi_f:     device FP32 table (required for VDW_FP32C, else ignored).
+ *   ws, ws_bytes: device workspace of at least enl_workspace_size() bytes.
+ *   E_out:     host, 3 doubles: {E_pair0, E_pairL, E_self} (Hartree).
+ * Errors: VDW_EINVAL, VDW_EUNSUPPORTED, VDW_EWORKSPACE, VDW_EHIP.
+ * ------------------------------------------------------------------- */
+int enl_energy(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *phi_d,
+               const float *phi_f, const vdw_table_params *tp, const vdw_opts *opts, void *ws,
+               size_t ws_bytes, double *E_out, void *stream);
+
+/* ---------------------------------------------------------------------
+ * enl_potential -- the energy of enl_energy and its derivative
+ *   dEdn_d[k] = dE / dn_k  at every grid point k,
+ * through n directly, through q0(n, |grad n|^2) and through the gradient
+ * stencil (dropped points pick up their share via the transposed stencil).
+ * The potential is v_nl = dEdn / dV.
+ *   grad_d, dq_dn_d, dq_dg_d: device, from compute_q0 on the same density.
+ *   dEdn_d: device, G doubles (written).
+ * Other arguments and errors as enl_energy.
+ * ------------------------------------------------------------------- */
+int enl_potential(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *grad_d,
+                  const double *dq_dn_d, const double *dq_dg_d, const double *phi_d, const float *phi_f,
+                  const vdw_table_params *tp, const vdw_opts *opts, void *ws, size_t ws_bytes,
+                  double *dEdn_d, double *E_out, void *stream);
+
+/* Bytes of workspace enl_potential_batched needs for these B grids. */
+size_t enl_batched_workspace_size(int32_t B, const vdw_grid *grids, const vdw_table_params *tp,
+                                  const vdw_opts *opts);
+
+/* ---------------------------------------------------------------------
+ * enl_potential_batched -- enl_potential for B independent densities of
+ * uneven sizes in one pass: one compaction over the packed grids, then one
+ * persistent pair-kernel launch that takes (density, i-block, j-chunk)
+ * work items from a shared list, then per-density reductions.
+ *   grids:    host, B grid descriptors (each non-periodic or periodic as
+ *             for enl_potential; opts apply to all).
+ *   grid_off: host, B+1 offsets: density b occupies elements
+ *             [grid_off[b], grid_off[b+1]) of the packed n/q0/dq/dEdn
+ *             arrays, and 3 planes of that size in grad_d at offset
+ *             3*grid_off[b].
+ *   E_out:    host, 3B doubles, {E_pair0, E_pairL, E_self} per density.
+ * Errors as enl_potential; VDW_EINVAL when offsets do not match the grids.
+ * ------------------------------------------------------------------- */
+int enl_potential_batched(int32_t B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d,
+                          const double *q0_d, const double *grad_d, const double *dq_dn_d,
+                          const double *dq_dg_d, const double *phi_d, const float *phi_f,
+                          const vdw_table_params *tp, const vdw_opts *opts, void *ws, size_t ws_bytes,
+                          double *dEdn_d, double *E_out, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Diagnostics of the last enl_* call on this host thread (after it
+ * returned VDW_OK): retained points, logical pairs (ordered (i, j, L),
+ * self pair excluded, before the distance cut), and kernel time of the
+ * pair kernel in milliseconds measured with HIP events on `stream`
+ * (0 unless timing was enabled with vdw_set_timing(1)).
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int64_t retained;
+    double  pairs;
+    float   pair_kernel_ms;
+    int32_t lds_rows;
+    int32_t block_threads;
+    int32_t j_chunks;
+    int32_t grid_blocks;
+} vdw_stats;
+
+int vdw_last_stats(vdw_stats *out);
+void vdw_set_timing(int32_t on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VDWDF_H */

@@ -1,0 +1,517 @@
+"""TEST ORACLE for the vdW-DF nonlocal-correlation path (test infrastructure).
+
+Plain FP64 CPU reference of everything the GPU library computes.  It is
+written from the mathematics of Lazic et al. (arXiv:0810.2273), Sec. 2
+(Eqs. 1-2, the kernel of Dion et al. and its large-D asymptote), Sec. 3
+(gradient, density cut-off, 0th cell plus periodic repetition), and from
+the two published ingredients that paper builds on: the Dion et al. q0
+(LDA exchange-correlation plus gradient term) and the Perdew-Wang 1992
+LDA correlation.  The heavy loops (quadrature of the kernel, the double
+sum) live in vdw_oracle.c; the O(grid) steps are numpy/scipy here.
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may use
+this module.  It shares no code with the HIP library and does not import
+it.  Every function is pinned by tests/test_oracle_*.py.
+
+Units: Hartree atomic units (bohr, Hartree, electrons / bohr^3).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "liboracle.so")
+_lib = None
+
+
+class TableParams(ct.Structure):
+    """Table layout and quadrature rule (mirrors vo_table_params)."""
+
+    _fields_ = [
+        ("n_D", ct.c_int32),
+        ("n_sigma", ct.c_int32),
+        ("D_max", ct.c_double),
+        ("gl_points", ct.c_int32),
+        ("graded_levels", ct.c_int32),
+        ("kappa", ct.c_double),
+        ("A0", ct.c_double),
+    ]
+
+
+def table_params(n_D=1024, n_sigma=32, D_max=48.0, gl_points=8, graded_levels=12, kappa=4.0, A0=64.0):
+    return TableParams(n_D, n_sigma, D_max, gl_points, graded_levels, kappa, A0)
+
+
+def lib():
+    """Load liboracle.so, building it with gcc if it is not there yet."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+
+        _b.build()
+    L = ct.CDLL(_LIB_PATH)
+    d, i32, i64, P = ct.c_double, ct.c_int32, ct.c_int64, ct.POINTER
+    dp = P(d)
+    L.vo_asym_C.restype = d
+    L.vo_gauss_legendre.argtypes = [ct.c_int, dp, dp]
+    L.vo_U.restype = d
+    L.vo_U.argtypes = [d]
+    for f in (L.vo_W2, L.vo_W_literal, L.vo_nu):
+        f.restype = d
+        f.argtypes = [d, d]
+    L.vo_T.restype = d
+    L.vo_T.argtypes = [d, d, d, d]
+    L.vo_rule_nodes.restype = ct.c_int
+    L.vo_rule_nodes.argtypes = [d, d, P(TableParams), dp, dp, ct.c_int]
+    L.vo_dion_phi.restype = d
+    L.vo_dion_phi.argtypes = [d, d, P(TableParams)]
+    L.vo_phi_Dsigma.restype = d
+    L.vo_phi_Dsigma.argtypes = [d, d, P(TableParams)]
+    L.vo_build_table.restype = ct.c_int
+    L.vo_build_table.argtypes = [P(TableParams), dp]
+    L.vo_table_nodes.restype = ct.c_int
+    L.vo_table_nodes.argtypes = [P(TableParams), ct.c_long, P(i32), P(i32), dp]
+    L.vo_table_interp.restype = d
+    L.vo_table_interp.argtypes = [dp, P(TableParams), d, d, dp, dp]
+    L.vo_pair_phi.restype = d
+    L.vo_pair_phi.argtypes = [d, d, d, dp, P(TableParams), dp]
+    L.vo_self_phi.restype = d
+    L.vo_self_phi.argtypes = [d, d, dp, P(TableParams), dp]
+    L.vo_pair_rows.restype = ct.c_int
+    L.vo_pair_rows.argtypes = [
+        ct.c_long, P(i32), P(i32), P(i32), dp, dp,
+        dp, P(i32), P(i32), P(i32), d,
+        dp, P(TableParams), ct.c_long, P(i64), dp, dp, dp,
+    ]
+    L.vo_block_sum.restype = d
+    L.vo_block_sum.argtypes = [
+        ct.c_long, P(i32), ct.c_long, P(i32),
+        P(i32), P(i32), P(i32), dp, dp,
+        dp, P(i32), P(i32), P(i32), d, dp, P(TableParams),
+    ]
+    L.vo_num_threads.restype = ct.c_int
+    _lib = L
+    return L
+
+
+def _p(a, ctype):
+    return a.ctypes.data_as(ct.POINTER(ctype))
+
+
+def num_threads() -> int:
+    return int(lib().vo_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Kernel phi and its table (Sec. 2: phi by the double integral of Dion et al.;
+# Sec. 7: table limits and node counts fixed by refinement checks).
+# --------------------------------------------------------------------------
+
+def asym_C() -> float:
+    return float(lib().vo_asym_C())
+
+
+def gauss_legendre(n: int):
+    x = np.zeros(n)
+    w = np.zeros(n)
+    lib().vo_gauss_legendre(n, _p(x, ct.c_double), _p(w, ct.c_double))
+    return x, w
+
+
+def U(x):
+    return float(lib().vo_U(float(x)))
+
+
+def W2(a, b):
+    """a^2 b^2 W(a, b) in the cancellation-free grouping."""
+    return float(lib().vo_W2(float(a), float(b)))
+
+
+def W_literal(a, b):
+    return float(lib().vo_W_literal(float(a), float(b)))
+
+
+def T(w, x, y, z):
+    return float(lib().vo_T(w, x, y, z))
+
+
+def nu(y, d):
+    return float(lib().vo_nu(float(y), float(d)))
+
+
+def rule_nodes(d1, d2, tp):
+    n = lib().vo_rule_nodes(d1, d2, ct.byref(tp), None, None, 0)
+    a = np.zeros(n)
+    w = np.zeros(n)
+    lib().vo_rule_nodes(d1, d2, ct.byref(tp), _p(a, ct.c_double), _p(w, ct.c_double), n)
+    return a, w
+
+
+def dion_phi(d1, d2, tp) -> float:
+    return float(lib().vo_dion_phi(float(d1), float(d2), ct.byref(tp)))
+
+
+def phi_Dsigma(D, sigma, tp) -> float:
+    return float(lib().vo_phi_Dsigma(float(D), float(sigma), ct.byref(tp)))
+
+
+def build_table(tp) -> np.ndarray:
+    """phi(D_k, sigma_l), shape (n_D, n_sigma); row 0 linearly extrapolated."""
+    out = np.zeros((tp.n_D, tp.n_sigma))
+    rc = lib().vo_build_table(ct.byref(tp), _p(out, ct.c_double))
+    if rc != 0:
+        raise ValueError("bad table parameters")
+    return out
+
+
+def table_nodes(tp, k, l) -> np.ndarray:
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    l = np.ascontiguousarray(l, dtype=np.int32)
+    out = np.zeros(len(k))
+    lib().vo_table_nodes(ct.byref(tp), len(k), _p(k, ct.c_int32), _p(l, ct.c_int32), _p(out, ct.c_double))
+    return out
+
+
+def table_interp(tab, tp, D, sigma):
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    dD = ct.c_double()
+    dS = ct.c_double()
+    v = lib().vo_table_interp(_p(tab, ct.c_double), ct.byref(tp), float(D), float(sigma), ct.byref(dD), ct.byref(dS))
+    return float(v), dD.value, dS.value
+
+
+def pair_phi(qi, qj, r, tab, tp):
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    dq = ct.c_double()
+    v = lib().vo_pair_phi(float(qi), float(qj), float(r), _p(tab, ct.c_double), ct.byref(tp), ct.byref(dq))
+    return float(v), dq.value
+
+
+def self_phi(q, rho_s, tab, tp):
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    dq = ct.c_double()
+    v = lib().vo_self_phi(float(q), float(rho_s), _p(tab, ct.c_double), ct.byref(tp), ct.byref(dq))
+    return float(v), dq.value
+
+
+# --------------------------------------------------------------------------
+# Grid (Sec. 2: equidistant grid; this path takes orthorhombic cells).
+# --------------------------------------------------------------------------
+
+
+@dataclass
+class Grid:
+    """Equidistant orthorhombic grid; point (ix, iy, iz) = (ix hx, iy hy, iz hz).
+
+    Arrays are (nz, ny, nx) in C order, so x is the fastest index.
+    """
+
+    n: tuple  # (nx, ny, nz)
+    h: tuple  # (hx, hy, hz) bohr
+    periodic: tuple = (0, 0, 0)
+
+    @property
+    def G(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def dV(self) -> float:
+        return float(self.h[0] * self.h[1] * self.h[2])
+
+
+def cell_volume_element(cell, n) -> float:
+    """dV = |det(cell)| / (n0 n1 n2) for a general (possibly skew) cell."""
+    c = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    return abs(float(np.linalg.det(c))) / float(n[0] * n[1] * n[2])
+
+
+def diff_matrix_1d(N: int, h: float, periodic: bool) -> sp.csr_matrix:
+    """Second-order finite-difference d/dx on N equidistant points.
+
+    Central (f[i+1] - f[i-1]) / 2h inside; periodic wrap on periodic axes;
+    one-sided (-3 f0 + 4 f1 - f2) / 2h and (3 f[N-1] - 4 f[N-2] + f[N-3]) / 2h
+    at the two faces of a non-periodic axis.
+    """
+    if N < 3:
+        raise ValueError("need at least 3 points per axis")
+    rows, cols, vals = [], [], []
+    c = 1.0 / (2.0 * h)
+    for i in range(N):
+        if periodic:
+            rows += [i, i]
+            cols += [(i + 1) % N, (i - 1) % N]
+            vals += [c, -c]
+        elif i == 0:
+            rows += [0, 0, 0]
+            cols += [0, 1, 2]
+            vals += [-3 * c, 4 * c, -c]
+        elif i == N - 1:
+            rows += [i, i, i]
+            cols += [N - 3, N - 2, N - 1]
+            vals += [c, -4 * c, 3 * c]
+        else:
+            rows += [i, i]
+            cols += [i + 1, i - 1]
+            vals += [c, -c]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+
+
+def gradient_operators(grid: Grid):
+    """Sparse G x G operators (Gx, Gy, Gz) on the flattened (x fastest) grid."""
+    nx, ny, nz = grid.n
+    Ix, Iy, Iz = sp.identity(nx), sp.identity(ny), sp.identity(nz)
+    Dx = diff_matrix_1d(nx, grid.h[0], bool(grid.periodic[0]))
+    Dy = diff_matrix_1d(ny, grid.h[1], bool(grid.periodic[1]))
+    Dz = diff_matrix_1d(nz, grid.h[2], bool(grid.periodic[2]))
+    Gx = sp.kron(Iz, sp.kron(Iy, Dx)).tocsr()
+    Gy = sp.kron(Iz, sp.kron(Dy, Ix)).tocsr()
+    Gz = sp.kron(Dz, sp.kron(Iy, Ix)).tocsr()
+    return Gx, Gy, Gz
+
+
+def gradient(grid: Grid, rho: np.ndarray):
+    """(dn/dx, dn/dy, dn/dz) on the flattened grid."""
+    r = np.asarray(rho, dtype=np.float64).reshape(-1)
+    return tuple(G @ r for G in gradient_operators(grid))
+
+
+# --------------------------------------------------------------------------
+# LDA correlation (Perdew-Wang 1992, unpolarised) and q0 (Dion et al.).
+# --------------------------------------------------------------------------
+
+PW92_A = 0.031091
+PW92_ALPHA1 = 0.21370
+PW92_BETA = (7.5957, 3.5876, 1.6382, 0.49294)
+Z_AB = -0.8491
+
+
+def pw92_ec(rs):
+    """eps_c(r_s) = -2A (1 + a1 rs) ln(1 + 1/Q), Q = 2A(b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2),
+    and its derivative in r_s.  The logarithm is taken as log1p(1/Q)."""
+    rs = np.asarray(rs, dtype=np.float64)
+    b1, b2, b3, b4 = PW92_BETA
+    A, a1 = PW92_A, PW92_ALPHA1
+    s = np.sqrt(rs)
+    Q = 2.0 * A * (b1 * s + b2 * rs + b3 * rs * s + b4 * rs * rs)
+    L = np.log1p(1.0 / Q)
+    ec = -2.0 * A * (1.0 + a1 * rs) * L
+    dQ = 2.0 * A * (0.5 * b1 / s + b2 + 1.5 * b3 * s + 2.0 * b4 * rs)
+    dec = -2.0 * A * a1 * L + 2.0 * A * (1.0 + a1 * rs) * dQ / (Q * (Q + 1.0))
+    return ec, dec
+
+
+def q0_of(n, g):
+    """q0 = -(4 pi / 3) eps_xc^0 with eps_xc^0 = eps_x^LDA + eps_c^LDA - eps_x^LDA (Z_ab / 9) s^2,
+    s = |grad n| / (2 k_F n).  Equivalent form used here:
+        q0 = k_F - (4 pi / 3) eps_c(r_s) - (Z_ab / 36) g / (k_F n^2),  g = |grad n|^2.
+    Returns (q0, dq0/dn at fixed g, dq0/dg)."""
+    n = np.asarray(n, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    kF = np.cbrt(3.0 * math.pi ** 2 * n)
+    rs = np.cbrt(3.0 / (4.0 * math.pi * n))
+    ec, dec = pw92_ec(rs)
+    q = kF - (4.0 * math.pi / 3.0) * ec - (Z_AB / 36.0) * g / (kF * n * n)
+    dq_dn = kF / (3.0 * n) + (4.0 * math.pi / 3.0) * dec * rs / (3.0 * n) + 7.0 * Z_AB * g / (108.0 * kF * n ** 3)
+    dq_dg = -Z_AB / (36.0 * kF * n * n)
+    return q, dq_dn, dq_dg
+
+
+def compute_q0(grid: Grid, rho, n_cut):
+    """Gradient, then q0 and its derivatives on the retained points n >= n_cut (0 elsewhere)."""
+    r = np.asarray(rho, dtype=np.float64).reshape(-1)
+    gx, gy, gz = gradient(grid, r)
+    g = gx * gx + gy * gy + gz * gz
+    keep = r >= n_cut
+    q = np.zeros_like(r)
+    dqdn = np.zeros_like(r)
+    dqdg = np.zeros_like(r)
+    qq, a, b = q0_of(r[keep], g[keep])
+    q[keep], dqdn[keep], dqdg[keep] = qq, a, b
+    return dict(gx=gx, gy=gy, gz=gz, g=g, q0=q, dq_dn=dqdn, dq_dg=dqdg, keep=keep)
+
+
+# --------------------------------------------------------------------------
+# The double sum of Eq. (2) with the self term, and its derivative.
+# --------------------------------------------------------------------------
+
+
+def self_radius(dV: float) -> float:
+    """rho_s = (3 dV / 4 pi)^(1/3) e^(-1/3): for phi = c - b ln D the mean of
+    phi(q r) over a ball of volume dV equals phi(q rho_s)."""
+    return (3.0 * dV / (4.0 * math.pi)) ** (1.0 / 3.0) * math.exp(-1.0 / 3.0)
+
+
+def _points(grid: Grid, keep):
+    idx = np.flatnonzero(keep)
+    nx, ny, _ = grid.n
+    ix = (idx % nx).astype(np.int32)
+    iy = ((idx // nx) % ny).astype(np.int32)
+    iz = (idx // (nx * ny)).astype(np.int32)
+    return idx, ix, iy, iz
+
+
+def pair_rows(grid: Grid, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), r_cut=0.0, rows=None):
+    """Per-row sums S0 (0th cell), S0 (images), Sq over all j and images."""
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    iz = np.ascontiguousarray(iz, dtype=np.int32)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    h = np.asarray(grid.h, dtype=np.float64)
+    gd = np.asarray(grid.n, dtype=np.int32)
+    per = np.asarray(grid.periodic, dtype=np.int32)
+    im = np.asarray(image_max, dtype=np.int32)
+    if rows is None:
+        nrows = len(n)
+        rows_p = None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows = len(rows)
+        rows_p = _p(rows, ct.c_int64)
+    S0c = np.zeros(nrows)
+    S0i = np.zeros(nrows)
+    Sq = np.zeros(nrows)
+    lib().vo_pair_rows(
+        len(n), _p(ix, ct.c_int32), _p(iy, ct.c_int32), _p(iz, ct.c_int32), _p(n, ct.c_double), _p(q, ct.c_double),
+        _p(h, ct.c_double), _p(gd, ct.c_int32), _p(per, ct.c_int32), _p(im, ct.c_int32), float(r_cut),
+        _p(tab, ct.c_double), ct.byref(tp), nrows, rows_p, _p(S0c, ct.c_double), _p(S0i, ct.c_double), _p(Sq, ct.c_double),
+    )
+    return S0c, S0i, Sq
+
+
+def block_sum(grid: Grid, A, B, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), r_cut=0.0):
+    """sum_{a in A, b in B} n_a n_b phi~_ab over images, skipping (a, a, 0)."""
+    A = np.ascontiguousarray(A, dtype=np.int32)
+    B = np.ascontiguousarray(B, dtype=np.int32)
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    iz = np.ascontiguousarray(iz, dtype=np.int32)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    h = np.asarray(grid.h, dtype=np.float64)
+    gd = np.asarray(grid.n, dtype=np.int32)
+    per = np.asarray(grid.periodic, dtype=np.int32)
+    im = np.asarray(image_max, dtype=np.int32)
+    return float(lib().vo_block_sum(
+        len(A), _p(A, ct.c_int32), len(B), _p(B, ct.c_int32),
+        _p(ix, ct.c_int32), _p(iy, ct.c_int32), _p(iz, ct.c_int32), _p(n, ct.c_double), _p(q, ct.c_double),
+        _p(h, ct.c_double), _p(gd, ct.c_int32), _p(per, ct.c_int32), _p(im, ct.c_int32), float(r_cut),
+        _p(tab, ct.c_double), ct.byref(tp)))
+
+
+@dataclass
+class Result:
+    E_pair0: float
+    E_pairL: float
+    E_self: float
+    dEdn: np.ndarray | None = None
+    S0: np.ndarray | None = None
+    Sq: np.ndarray | None = None
+    q0: dict | None = None
+
+    @property
+    def E(self) -> float:
+        return self.E_pair0 + self.E_pairL + self.E_self
+
+
+def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True, potential=False):
+    """E_c^nl = 1/2 dV^2 sum_{(i,j,L) != (i,i,0)} n_i n_j phi~ (Eq. 2 with the volume
+    element written out) + E_self, and optionally dE/dn at every grid point."""
+    r = np.asarray(rho, dtype=np.float64).reshape(-1)
+    qd = compute_q0(grid, r, n_cut)
+    keep = qd["keep"]
+    idx, ix, iy, iz = _points(grid, keep)
+    nS = r[idx]
+    qS = qd["q0"][idx]
+    dV = grid.dV
+    S0c, S0i, Sq = pair_rows(grid, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut)
+    E0 = 0.5 * dV * dV * float(np.sum(nS * S0c))
+    EL = 0.5 * dV * dV * float(np.sum(nS * S0i))
+    rs = self_radius(dV)
+    Phi = np.zeros(len(nS))
+    dPhi = np.zeros(len(nS))
+    if self_term:
+        for t in range(len(nS)):
+            Phi[t], dPhi[t] = self_phi(qS[t], rs, tab, tp)
+    Es = 0.5 * dV * dV * float(np.sum(nS * nS * Phi))
+    res = Result(E0, EL, Es, S0=S0c + S0i, Sq=Sq, q0=qd)
+    if potential:
+        res.dEdn = adjoint(grid, r, qd, idx, nS, S0c + S0i, Sq, Phi, dPhi)
+    return res
+
+
+def adjoint(grid: Grid, rho, qd, idx, nS, S0, Sq, Phi, dPhi):
+    """dE/dn_k on the whole grid.
+
+    For k retained:  dE/dn_k|_q = dV^2 (S0_k + n_k Phi_k),
+                     dE/dq_k    = dV^2 n_k (Sq_k + 1/2 n_k dPhi_k),
+    and q_k depends on n_k directly and on g = |grad n|^2 of the
+    finite-difference gradient, so
+       v = [k in S](dE/dn|_q + dE/dq dq/dn) + sum_a G_a^T B_a,
+       B_a = [i in S] dE/dq_i dq/dg_i 2 (d_a n)_i,
+    with G_a the gradient operators (the transpose makes dropped points
+    that feed a retained point's stencil pick up their share)."""
+    dV = grid.dV
+    G = grid.G
+    dEdn_q = dV * dV * (S0 + nS * Phi)
+    dEdq = dV * dV * nS * (Sq + 0.5 * nS * dPhi)
+    v = np.zeros(G)
+    v[idx] = dEdn_q + dEdq * qd["dq_dn"][idx]
+    ops = gradient_operators(grid)
+    for Ga, comp in zip(ops, ("gx", "gy", "gz")):
+        B = np.zeros(G)
+        B[idx] = dEdq * qd["dq_dg"][idx] * 2.0 * qd[comp][idx]
+        v += Ga.T @ B
+    return v
+
+
+def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True):
+    """E(n + eps e_k) - E(n - eps e_k), recomputing only the rows whose n or
+    q change (k and its finite-difference neighbours).  With P that set:
+      sum over all pairs = (pairs outside P) + 2 R(P) - PP,
+      R(P) = sum_{i in P, j} n_i n_j phi~_ij,  PP = sum_{i, j in P}."""
+    r0 = np.asarray(rho, dtype=np.float64).reshape(-1).copy()
+    ops = gradient_operators(grid)
+    touched = set([int(k)])
+    for Ga in ops:
+        col = Ga.getcol(int(k)).tocoo()
+        touched.update(int(i) for i in col.row)
+    keep = r0 >= n_cut
+    idx, ix, iy, iz = _points(grid, keep)
+    pos = {int(g): t for t, g in enumerate(idx)}
+    P = np.array(sorted(pos[g] for g in touched if g in pos), dtype=np.int32)
+    allS = np.arange(len(idx), dtype=np.int32)
+    dV = grid.dV
+    rs = self_radius(dV)
+
+    def part(rr):
+        gx, gy, gz = (Ga @ rr for Ga in ops)
+        g = gx * gx + gy * gy + gz * gz
+        q = np.zeros_like(rr)
+        q[keep] = q0_of(rr[keep], g[keep])[0]
+        nS, qS = rr[idx], q[idx]
+        R = block_sum(grid, P, allS, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut)
+        PP = block_sum(grid, P, P, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut)
+        e = 0.5 * dV * dV * (2.0 * R - PP)
+        if self_term:
+            for t in P:
+                e += 0.5 * dV * dV * nS[t] * nS[t] * self_phi(qS[t], rs, tab, tp)[0]
+        return e
+
+    rp = r0.copy()
+    rp[k] += eps
+    rm = r0.copy()
+    rm[k] -= eps
+    if not (np.array_equal(rp >= n_cut, keep) and np.array_equal(rm >= n_cut, keep)):
+        raise ValueError("perturbation changes the retained set")
+    return part(rp) - part(rm)
