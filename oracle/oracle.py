@@ -515,3 +515,55 @@ def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0
     if not (np.array_equal(rp >= n_cut, keep) and np.array_equal(rm >= n_cut, keep)):
         raise ValueError("perturbation changes the retained set")
     return part(rp) - part(rm)
+
+
+def potential_at(grid: Grid, rho, ks, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True):
+    """dE/dn_k at the grid points ks only: the rows of the double sum that
+    the formula of `adjoint` needs at k (k itself and the kept points whose
+    gradient stencil contains k) are summed over every j, nothing else.
+    Same arithmetic as `evaluate(..., potential=True)` restricted to ks."""
+    r = np.asarray(rho, dtype=np.float64).reshape(-1)
+    qd = compute_q0(grid, r, n_cut)
+    keep = qd["keep"]
+    idx, ix, iy, iz = _points(grid, keep)
+    pos = {int(g): t for t, g in enumerate(idx)}
+    ops = gradient_operators(grid)
+    cols = [Ga.tocsc() for Ga in ops]
+    need = set()
+    for k in ks:
+        k = int(k)
+        if keep[k]:
+            need.add(k)
+        for Gc in cols:
+            need.update(int(i) for i in Gc.getcol(k).indices if keep[int(i)])
+    gl = np.array(sorted(need), dtype=np.int64)
+    rows = np.array([pos[int(g)] for g in gl], dtype=np.int64)
+    nS, qS = r[idx], qd["q0"][idx]
+    if len(rows):
+        S0c, S0i, Sq = pair_rows(grid, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut, rows=rows)
+    else:
+        S0c = S0i = Sq = np.zeros(0)
+    dV = grid.dV
+    rs = self_radius(dV)
+    dEdn_q = {}
+    dEdq = {}
+    for t, g in enumerate(gl):
+        n = r[g]
+        Phi, dPhi = self_phi(qS[rows[t]], rs, tab, tp) if self_term else (0.0, 0.0)
+        dEdn_q[int(g)] = dV * dV * (S0c[t] + S0i[t] + n * Phi)
+        dEdq[int(g)] = dV * dV * n * (Sq[t] + 0.5 * n * dPhi)
+    out = np.zeros(len(ks))
+    comps = (qd["gx"], qd["gy"], qd["gz"])
+    for s, k in enumerate(ks):
+        k = int(k)
+        v = 0.0
+        if keep[k]:
+            v += dEdn_q[k] + dEdq[k] * qd["dq_dn"][k]
+        for Gc, ga in zip(cols, comps):
+            col = Gc.getcol(k)
+            for i, c in zip(col.indices, col.data):
+                i = int(i)
+                if keep[i]:
+                    v += c * dEdq[i] * qd["dq_dg"][i] * 2.0 * ga[i]
+        out[s] = v
+    return out

@@ -1,0 +1,92 @@
+// Error reporting, argument validation and device queries for libvdwdf.so.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.h"
+
+namespace vdw {
+
+static thread_local char g_err[512] = "no error";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int validate_grid(const vdw_grid *g, GridDev *out)
+{
+    if (!g) return fail(VDW_EINVAL, "grid is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 3) return fail(VDW_EINVAL, "grid n[%d] = %d < 3", a, g->n[a]);
+        for (int b = 0; b < 3; ++b) {
+            double v = g->cell[a][b];
+            if (!isfinite(v)) return fail(VDW_EINVAL, "cell[%d][%d] is not finite", a, b);
+            if (a != b && v != 0.0)
+                return fail(VDW_EUNSUPPORTED,
+                            "non-orthorhombic cell (cell[%d][%d] = %g): the finite-difference "
+                            "gradient needs perpendicular axes", a, b, v);
+        }
+        if (!(g->cell[a][a] > 0.0)) return fail(VDW_EINVAL, "cell[%d][%d] must be > 0", a, a);
+        if (g->periodic[a] != 0 && g->periodic[a] != 1)
+            return fail(VDW_EINVAL, "periodic[%d] must be 0 or 1", a);
+    }
+    int64_t G = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    if (G > (int64_t)1 << 31) return fail(VDW_EINVAL, "grid too large (%lld points)", (long long)G);
+    if (out) {
+        out->nx = g->n[0];
+        out->ny = g->n[1];
+        out->nz = g->n[2];
+        out->px = g->periodic[0];
+        out->py = g->periodic[1];
+        out->pz = g->periodic[2];
+        out->hx = g->cell[0][0] / g->n[0];
+        out->hy = g->cell[1][1] / g->n[1];
+        out->hz = g->cell[2][2] / g->n[2];
+        out->G = G;
+    }
+    return VDW_OK;
+}
+
+int validate_table(const vdw_table_params *tp)
+{
+    if (!tp) return fail(VDW_EINVAL, "table params are NULL");
+    if (tp->n_D < 3) return fail(VDW_EINVAL, "n_D = %d < 3", tp->n_D);
+    if (tp->n_sigma < 2) return fail(VDW_EINVAL, "n_sigma = %d < 2", tp->n_sigma);
+    if ((int64_t)tp->n_D * tp->n_sigma > (int64_t)1 << 26) return fail(VDW_EINVAL, "table too large");
+    if (!(tp->D_max > 0.0) || !isfinite(tp->D_max)) return fail(VDW_EINVAL, "D_max must be > 0");
+    if (tp->gl_points < 2 || tp->gl_points > 32) return fail(VDW_EINVAL, "gl_points must be in 2..32");
+    if (tp->graded_levels < 0 || tp->graded_levels > 40) return fail(VDW_EINVAL, "graded_levels must be in 0..40");
+    if (!(tp->kappa > 0.0) || !(tp->A0 > 0.0) || !isfinite(tp->kappa) || !isfinite(tp->A0))
+        return fail(VDW_EINVAL, "kappa and A0 must be > 0");
+    return VDW_OK;
+}
+
+int device_info(DevInfo *out)
+{
+    static thread_local int cached_dev = -1;
+    static thread_local DevInfo cached;
+    int dev = 0;
+    VDW_HIP(hipGetDevice(&dev));
+    if (dev != cached_dev) {
+        hipDeviceProp_t p;
+        VDW_HIP(hipGetDeviceProperties(&p, dev));
+        cached.device = dev;
+        cached.cus = p.multiProcessorCount;
+        cached.lds_per_block = p.sharedMemPerBlock;
+        cached_dev = dev;
+    }
+    *out = cached;
+    return VDW_OK;
+}
+
+}  // namespace vdw
+
+extern "C" const char *vdw_last_error(void) { return vdw::g_err; }
+
+extern "C" const char *vdw_version(void) { return "vdwdf-mi355x 0.1 (gfx950)"; }
