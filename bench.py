@@ -42,6 +42,8 @@ def parse():
     p.add_argument("--lds-rows", type=int, default=-1)
     p.add_argument("--j-chunks", type=int, default=0)
     p.add_argument("--grid-blocks", type=int, default=0)
+    p.add_argument("--copy-calib", type=int, default=0,
+                   help="MiB: run one plain device-to-device copy of this size first (profiler calibration)")
     return p.parse_args()
 
 
@@ -58,6 +60,12 @@ def main():
     import vdw_workloads as W
 
     dev = torch.device("cuda:0")
+    if a.copy_calib > 0:
+        src = torch.ones(a.copy_calib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = W.kr_dimer(a.R)
     tparams = V.TableParams(n_D=2048, n_sigma=64, D_max=48.0)
     print(f"# building table {tparams.n_D}x{tparams.n_sigma} on the GPU", file=sys.stderr, flush=True)
