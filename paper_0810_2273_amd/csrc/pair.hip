@@ -7,17 +7,26 @@
 // before the final copy of the energies):
 //   fill      zero the work counter, flags, and (potential) dE/dn buffers
 //   count     brick-ordered scan of n >= n_cut, per-block counts
-//   scan      one workgroup: exclusive prefix, per-density point/item offsets
+//   scan      one workgroup: exclusive prefix, per-density offsets and the
+//             work-item table
 //   scatter   compact the kept points into 32-byte (FP32) or 64-byte (FP64)
-//             records in brick order (4x4x4 bricks, so a wavefront's 64
+//             records in brick order (4x4x4 bricks, so a wavefront's
 //             i-points are spatially compact and their table rows coherent)
-//   pair      persistent workgroups pull (density, i-block, j-chunk) items
-//             from an atomic counter; each lane owns one i-point, the j
-//             records stream through scalar registers (wave-uniform loads),
-//             the first table rows sit in LDS (row stride n_sigma + 1 so a
-//             column spread over rows hits different banks), the rest is
-//             read through L2; partial sums go to per-chunk slots
-//   finalize  per point: fixed-order sum of the chunk partials, on-site term,
+//   pair      persistent workgroups pull work items from an atomic counter.
+//             The kept points of a density are cut into row blocks of 2048
+//             (two i-points per lane).  Row block I owns one diagonal item
+//             (ordered pairs inside the block, j records streamed through
+//             scalar registers) and items (I, c) pairing it with chunks of
+//             the points after the block.  Off-diagonal pairs are evaluated
+//             once for both orders: each wavefront loads a 64-record j tile
+//             into its lanes and rotates it one lane per step (DPP wave
+//             rotate), carrying the j-side sums with the records, so after
+//             64 steps every lane has met every j and every j-side sum is
+//             back in its home lane; the 16 wavefronts then add their
+//             j-side sums in a fixed order through LDS.  The first table
+//             rows sit in LDS (row stride n_sigma + 1), the rest is read
+//             through L2.
+//   finalize  per point: fixed-order sum of its item partials, on-site term,
 //             energy terms, and (potential) the direct part of dE/dn
 //   reduce    per density: fixed-order sum of the block partials
 //   assemble  (potential) transposed gradient stencil on the whole grid
@@ -34,9 +43,11 @@ namespace {
 
 constexpr int kCompactBlock = 1024;  // brick-order positions per count/scatter block
 constexpr int kCompactThreads = 256;  // 4 positions (one brick row) per thread
-constexpr int kPairThreads = 1024;    // i-points per item (one per lane)
+constexpr int kPairThreads = 1024;    // threads of a pair workgroup
+constexpr int kWaves = kPairThreads / 64;
+constexpr int kBI = 2 * kPairThreads; // i-points per row block (two per lane)
 constexpr int kFinThreads = 256;      // points per finalize block
-constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 carry
+constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 carry (diagonal items)
 
 enum { HDR_ITEMS = 0, HDR_NTOTAL = 1, HDR_BLKS = 2, HDR_WORDS = 8 };
 
@@ -45,10 +56,12 @@ struct Seg {
     int32_t nx, ny, nz, px, py, pz;
     double hx, hy, hz, dV;
     int64_t G, grid_off;
-    int32_t nbx, nby, nbz, C;
-    int64_t t_off, T;  // brick-order positions: offset (multiple of kCompactBlock), padded length
+    int32_t nbx, nby, nbz, pad0;
+    int64_t t_off, T;     // brick-order positions: offset (multiple of kCompactBlock), padded length
+    int64_t row_base;     // first entry of this density in the row-offset table
+    int64_t slot_base;    // first partial slot of this density
     // filled on the device by scan_kernel
-    int64_t N, p_off, part_off, item_off, blk_off, nIB;
+    int64_t N, p_off, item_off, blk_off, nIB, items;
 };
 
 struct alignas(32) RecF {
@@ -144,7 +157,8 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(const Seg *__res
 // One workgroup: exclusive prefix of the block counts (in place, with the
 // total appended), then the per-density offsets the later kernels use.
 __global__ __launch_bounds__(1024) void scan_kernel(int64_t *__restrict__ counts, int64_t nblocks,
-                                                    Seg *__restrict__ segs, int B, int64_t *__restrict__ hdr)
+                                                    Seg *__restrict__ segs, int B, int64_t *__restrict__ hdr,
+                                                    int64_t *__restrict__ rowoff, int64_t JC)
 {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
@@ -170,18 +184,25 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t *__restrict__ counts
     if (t == 1023) counts[nblocks] = part[1023];
     __syncthreads();
     if (t == 0) {
-        int64_t part_off = 0, item_off = 0, blk_off = 0;
+        int64_t item_off = 0, blk_off = 0;
         for (int b = 0; b < B; ++b) {
             Seg &g = segs[b];
             int64_t first = g.t_off / kCompactBlock, last = (g.t_off + g.T) / kCompactBlock;
             g.p_off = counts[first];
             g.N = counts[last] - counts[first];
-            g.nIB = (g.N + kPairThreads - 1) / kPairThreads;
-            g.part_off = part_off;
+            g.nIB = (g.N + kBI - 1) / kBI;
+            // row I: one diagonal item, then ceil((N - (I+1) kBI) / JC) chunks
+            int64_t items = 0;
+            for (int64_t I = 0; I < g.nIB; ++I) {
+                rowoff[g.row_base + I] = items;
+                int64_t rest = g.N - (I + 1) * kBI;
+                items += 1 + (rest > 0 ? (rest + JC - 1) / JC : 0);
+            }
+            rowoff[g.row_base + g.nIB] = items;
+            g.items = items;
             g.item_off = item_off;
             g.blk_off = blk_off;
-            part_off += (int64_t)g.C * g.N;
-            item_off += g.nIB * g.C;
+            item_off += items;
             blk_off += (g.N + kFinThreads - 1) / kFinThreads;
         }
         hdr[HDR_ITEMS] = item_off;
@@ -199,7 +220,7 @@ struct ScatterArgs {
     const int64_t *offs;
     void *recs;
     int32_t *gidx;
-    double inv2dD;  // 1 / (2 dD): a = q / (2 dD) is D per unit distance in table-index units
+    double inv2dD;  // 1 / (2 dD): a = q h_x / (2 dD) is D / dD per grid spacing h_x
     double csig;    // sqrt(n_sigma - 1): b = csig a, so (b_i - b_j)/(a_i + a_j) = csig delta
     int fp64;
 };
@@ -241,7 +262,7 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
     for (int u = 0; u < 4; ++u) {
         if (!keep[u]) continue;
         double nn = A.n[gi[u]], q = A.q0[gi[u]];
-        double a = q * A.inv2dD;
+        double a = q * s.hx * A.inv2dD;
         if (A.fp64) {
             RecD r;
             r.x = xs[u];
@@ -275,22 +296,19 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
 // ---------------------------------------------------------------------------
 
 struct PairArgs {
-    const void *recs;
-    const Seg *segs;
     int B;
-    const int64_t *hdr;
-    int *counter;
-    const void *tabg;   // full table in global memory (float or double)
     int nD, nS, S, K;   // S: LDS row stride (n_sigma + 1); K: rows held in LDS
+    int JC;             // j-points per off-diagonal item (multiple of 64)
     double tDmax;       // n_D - 1: table branch iff t_D = D / dD < n_D - 1
     double tSclamp;     // largest value below n_sigma - 1 (sigma index clamp)
-    double casym;       // C = 12 (4 pi/9)^3
+    double csig;        // sqrt(n_sigma - 1)
+    double casym;       // C / (2 dD)^6, C = 12 (4 pi/9)^3 (asymptote in h_x units)
     double dD2;         // 2 dD
     double rc2;         // squared distance cut (inf: none)
-    const int *imgs;    // image multipliers (m_x, m_y, m_z, 0) per image
     int nimg, home;     // number of images, index of (0, 0, 0)
-    double *part;       // chunk partials
-    int64_t part_stride;  // doubles per accumulator array
+    int NI, NJ;         // accumulator arrays: S0c, (S0L if images), (Sq if potential)
+    int64_t istride;    // doubles per i-side accumulator array
+    int64_t jstride;    // elements per j-side accumulator array
 };
 
 template <typename R>
@@ -311,38 +329,142 @@ __device__ inline double drcp(double x) { return 1.0 / x; }
 __device__ inline float dfract(float x) { return __builtin_amdgcn_fractf(x); }
 __device__ inline double dfract(double x) { return x - floor(x); }
 
+// Rotate a wavefront-wide value by one lane (DPP wave_ror:1): 64 rotations
+// bring every value back to its lane.
+__device__ inline float wrot(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x13C, 0xF, 0xF, true));
+}
+__device__ inline double wrot(double x)
+{
+    int2 v = __builtin_bit_cast(int2, x);
+    v.x = __builtin_amdgcn_mov_dpp(v.x, 0x13C, 0xF, 0xF, true);
+    v.y = __builtin_amdgcn_mov_dpp(v.y, 0x13C, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, v);
+}
+
+template <typename R>
+struct PairK {
+    R tDmax, tSclamp, csig, c4, casym, wy, wz;
+    int S, nS, K;
+};
+
+__device__ inline float dmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ inline double dmin(double a, double b) { return __builtin_fmin(a, b); }
+
+// Squared distance in units of h_x^2 from exact integer grid deltas
+// (wy = (h_y/h_x)^2, wz = (h_z/h_x)^2; both 1 on cubic grids).
+template <typename R, bool CUBIC>
+__device__ __forceinline__ R dist2(const PairK<R> &k, R dx, R dy, R dz)
+{
+    if (CUBIC) return dx * dx + dy * dy + dz * dz;
+    return dx * dx + (k.wy * dy) * dy + (k.wz * dz) * dz;
+}
+
+// phi~ of one pair and (ADJ) the q-derivatives, from m = r^2 / h_x^2 and
+// a = q h_x / (2 dD) of both points (b_i = csig a_i):
+//   t_D = (a_i + a_j) sqrt(m) = D / dD,  u = csig (a_i - a_j)/(a_i + a_j),  t_s = u^2 = sigma (n_sigma - 1)
+//   table branch: bilinear in (t_D, t_s);  beyond: -C' / (m^3 a_i^2 a_j^2 (a_i^2 + a_j^2)),  C' = C / (2 dD)^6
+// dqi, dqj are 2 dD / h_x times d phi~ / d q_i and d phi~ / d q_j.
+template <typename R, bool ADJ, bool JSIDE, int NSIG>
+__device__ __forceinline__ void pair_eval(const PairK<R> &k, const R *tab, const R *__restrict__ tabg, R m, R ai,
+                                          R bi, R aj, R caj, R &phi, R &dqi, R &dqj)
+{
+    const int S = NSIG ? NSIG + 1 : k.S;
+    const int nS = NSIG ? NSIG : k.nS;
+    const R r = dsqrt(m);
+    const R s = ai + aj;
+    const R tD = s * r;
+    if (tD < k.tDmax) {
+        const R inv = drcp(s);
+        const R u = (bi - caj) * inv;
+        const R ts = dmin(u * u, k.tSclamp);
+        const int kk = (int)tD;
+        const int l = (int)ts;
+        const R fD = dfract(tD), fS = dfract(ts);
+        // rows below K come from LDS; the clamped LDS read is always in
+        // bounds and is replaced for rows >= K - 1
+        const int kl = min(kk, k.K - 2);
+        const int o = (int)__umul24((unsigned)kl, (unsigned)S) + l;
+        R p00 = tab[o], p01 = tab[o + 1], p10 = tab[o + S], p11 = tab[o + S + 1];
+        // keep the LDS reads unconditional: without this the compiler folds
+        // the two sources into one FLAT load
+        asm("" : "+v"(p00), "+v"(p01), "+v"(p10), "+v"(p11));
+        if (kk >= k.K - 1) {
+            const R *t0 = tabg + (int64_t)kk * nS + l;
+            p00 = t0[0];
+            p01 = t0[1];
+            p10 = t0[nS];
+            p11 = t0[nS + 1];
+        }
+        const R d0 = p01 - p00, d1 = p11 - p10;
+        const R lo = p00 + fS * d0, hi = p10 + fS * d1;
+        const R gD = hi - lo;
+        phi = lo + fD * gD;
+        if (ADJ) {
+            const R gS = d0 + fD * (d1 - d0);
+            // gD r + gS u inv^2 4 csig a_j;  for q_j the sigma term flips sign and a_j -> a_i
+            const R X = gD * r;
+            const R Y = (gS * (u * inv)) * (inv * k.c4);
+            dqi = X + Y * aj;
+            if (JSIDE) dqj = X - Y * ai;
+        }
+    } else {
+        // a private copy keeps these rare-branch products from being hoisted
+        R ajx = aj;
+        asm("" : "+v"(ajx));
+        const R pi = ai * ai, pj = ajx * ajx, pp = pi + pj;
+        phi = -k.casym * drcp(m * m * m * pi * pj * pp);
+        if (ADJ) {
+            const R rp = drcp(pp);
+            dqi = -phi * ((R)2 * drcp(ai) + (R)2 * ai * rp);
+            if (JSIDE) dqj = -phi * ((R)2 * drcp(ajx) + (R)2 * ajx * rp);
+        }
+    }
+}
+
 // Pointers are separate __restrict__ parameters so the compiler knows the
 // records, segments and table are not written during the kernel and can
-// fetch wave-uniform j records with scalar loads.
-template <typename R, bool ADJ, bool IMG, bool KAHAN>
+// fetch wave-uniform records with scalar loads.
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC>
 __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const typename RecOf<R>::T *__restrict__ recs,
                                                             const Seg *__restrict__ segs,
                                                             const int64_t *__restrict__ hdr, int *__restrict__ counter,
                                                             const R *__restrict__ tabg, const int *__restrict__ imgs,
-                                                            double *__restrict__ part)
+                                                            const int64_t *__restrict__ rowoff,
+                                                            double *__restrict__ ipart, R *__restrict__ jpart)
 {
     using Rec = typename RecOf<R>::T;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R *tab = reinterpret_cast<R *>(smem_raw);
-    __shared__ int s_item;
+    R *red = tab + A.K * A.S;  // [kWaves][NJ][64] j-side sums of one tile
+    int *s_item = reinterpret_cast<int *>(red + kWaves * A.NJ * 64);
 
-    const int S = A.S, nS = A.nS, K = A.K;
+    const int nS = A.nS;
+    PairK<R> kc;
+    kc.tDmax = (R)A.tDmax;
+    kc.tSclamp = (R)A.tSclamp;
+    kc.csig = (R)A.csig;
+    kc.c4 = (R)(4.0 * A.csig);
+    kc.casym = (R)A.casym;
+    kc.S = A.S;
+    kc.nS = nS;
+    kc.K = A.K;
 
-    for (int t = threadIdx.x; t < K * nS; t += kPairThreads) {
+    for (int t = threadIdx.x; t < A.K * nS; t += kPairThreads) {
         int r = t / nS, c = t - r * nS;
-        tab[r * S + c] = tabg[t];
+        tab[r * A.S + c] = tabg[t];
     }
     __syncthreads();
 
     const int64_t total = hdr[HDR_ITEMS];
-    const R tDmax = (R)A.tDmax, tSclamp = (R)A.tSclamp;
-    const R casym = (R)A.casym;
-    const R rc2 = (R)A.rc2;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int iS0L = 1, iSq = A.NI - 1;  // accumulator array indices
 
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        const int item = __builtin_amdgcn_readfirstlane(*s_item);
         __syncthreads();
         if (item >= total) break;
 
@@ -350,113 +472,204 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
         const Seg &sg = segs[b];
         const int N = __builtin_amdgcn_readfirstlane((int)sg.N);
         const int nIB = __builtin_amdgcn_readfirstlane((int)sg.nIB);
-        const int C = sg.C;
         const int local = __builtin_amdgcn_readfirstlane((int)(item - sg.item_off));
-        const int c = local / nIB;
-        const int ib = local - c * nIB;
-        const int len = (N + C - 1) / C;
-        const int j0 = min(N, c * len), j1 = min(N, j0 + len);
-        const R hx2 = (R)(sg.hx * sg.hx), hy2 = (R)(sg.hy * sg.hy), hz2 = (R)(sg.hz * sg.hz);
+        const int64_t *__restrict__ ro = rowoff + sg.row_base;
+        int I = 0;
+        {
+            int lo = 0, hi = nIB - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (ro[mid] <= local) lo = mid;
+                else hi = mid - 1;
+            }
+            I = __builtin_amdgcn_readfirstlane(lo);
+        }
+        const int c = local - (int)ro[I];
+        const int64_t slot = sg.slot_base + local;
+        kc.wy = (R)((sg.hy / sg.hx) * (sg.hy / sg.hx));
+        kc.wz = (R)((sg.hz / sg.hx) * (sg.hz / sg.hx));
+        const R rcm = (R)(A.rc2 / (sg.hx * sg.hx));  // distance cut in units of h_x^2
         const Rec *__restrict__ P = recs + sg.p_off;
 
-        const int il = ib * kPairThreads + threadIdx.x;
-        const bool active = il < N;
-        const Rec I = P[active ? il : N - 1];
-        const R xi = I.x, yi = I.y, zi = I.z, ai = I.a, bi = I.b, pi = I.p;
-        const R c1 = (R)2 / ai;                      // asymptote, 2 dD (2 / q_i) in a-units
-        const R c2 = (R)(A.dD2 * A.dD2 * 2.0) * ai;  // asymptote, 2 dD (2 q_i)
+        // two i-points per lane
+        const int ila = I * kBI + w * 128 + lane, ilb = ila + 64;
+        const bool acta = ila < N, actb = ilb < N;
+        const Rec Ia = P[acta ? ila : N - 1], Ib = P[actb ? ilb : N - 1];
+        const R nia = acta ? Ia.n : (R)0, nib = actb ? Ib.n : (R)0;
 
-        double S0c = 0.0, S0L = 0.0, Sq = 0.0;
-
+        double Sc_a = 0.0, SL_a = 0.0, Sq_a = 0.0, Sc_b = 0.0, SL_b = 0.0, Sq_b = 0.0;
         const int nimg = IMG ? A.nimg : 1;
-        for (int L = 0; L < nimg; ++L) {
-            R sx = xi, sy = yi, sz = zi;
-            bool home = true;
-            if (IMG) {
-                sx -= (R)(imgs[4 * L + 0] * sg.nx);
-                sy -= (R)(imgs[4 * L + 1] * sg.ny);
-                sz -= (R)(imgs[4 * L + 2] * sg.nz);
-                home = (L == A.home);
-            }
-            if (j0 >= j1) continue;
-            Rec Jn = P[j0];
-            for (int jr = j0; jr < j1; jr += kRun) {
-                const int je = min(j1, jr + kRun);
-                R acc = 0, accq = 0, cmp = 0, cmpq = 0;
-                for (int j = jr; j < je; ++j) {
-                    const Rec J = Jn;
-                    Jn = P[min(j + 1, j1 - 1)];  // prefetch the next record (wave-uniform)
-                    const R dx = sx - J.x, dy = sy - J.y, dz = sz - J.z;
-                    const R r2 = hx2 * (dx * dx) + hy2 * (dy * dy) + hz2 * (dz * dz);
-                    R w = (r2 > (R)0) ? J.n : (R)0;
-                    if (IMG) w = (r2 <= rc2) ? w : (R)0;
-                    const R r = dsqrt(r2);
-                    const R s = ai + J.a;
-                    const R tD = s * r;
-                    const R inv = drcp(s);
-                    const R u = (bi - J.b) * inv;
-                    R phi, dq = 0;
-                    if (tD < tDmax) {
-                        const R ts = (u * u < tSclamp) ? u * u : tSclamp;
-                        const int k = (int)tD;
-                        const int l = (int)ts;
-                        const R fD = dfract(tD), fS = dfract(ts);
-                        // rows below K come from LDS; the clamped LDS read is
-                        // always in bounds and is replaced for rows >= K - 1
-                        const int kl = min(k, K - 2);
-                        const int o = (int)__umul24((unsigned)kl, (unsigned)S) + l;
-                        R p00 = tab[o], p01 = tab[o + 1], p10 = tab[o + S], p11 = tab[o + S + 1];
-                        // keep the LDS reads unconditional: without this the
-                        // compiler folds the two sources into one FLAT load
-                        asm("" : "+v"(p00), "+v"(p01), "+v"(p10), "+v"(p11));
-                        if (k + 1 >= K) {
-                            const R *t0 = tabg + (int64_t)k * nS + l;
-                            p00 = t0[0];
-                            p01 = t0[1];
-                            p10 = t0[nS];
-                            p11 = t0[nS + 1];
+
+        if (c == 0) {
+            // diagonal item: ordered pairs inside the row block, j through scalar loads
+            const int j0 = I * kBI, j1 = min(N, j0 + kBI);
+            for (int L = 0; L < nimg; ++L) {
+                R sxa = Ia.x, sya = Ia.y, sza = Ia.z, sxb = Ib.x, syb = Ib.y, szb = Ib.z;
+                bool home = true;
+                if (IMG) {
+                    const R mx = (R)(imgs[4 * L + 0] * sg.nx), my = (R)(imgs[4 * L + 1] * sg.ny),
+                            mz = (R)(imgs[4 * L + 2] * sg.nz);
+                    sxa -= mx;
+                    sya -= my;
+                    sza -= mz;
+                    sxb -= mx;
+                    syb -= my;
+                    szb -= mz;
+                    home = (L == A.home);
+                }
+                Rec Jn = P[j0];
+                for (int jr = j0; jr < j1; jr += kRun) {
+                    const int je = min(j1, jr + kRun);
+                    R acca = 0, accqa = 0, accb = 0, accqb = 0, cma = 0, cmb = 0;
+                    for (int j = jr; j < je; ++j) {
+                        const Rec J = Jn;
+                        Jn = P[min(j + 1, j1 - 1)];  // prefetch the next record (wave-uniform)
+                        const R ma = dist2<R, CUBIC>(kc, sxa - J.x, sya - J.y, sza - J.z);
+                        const R mb = dist2<R, CUBIC>(kc, sxb - J.x, syb - J.y, szb - J.z);
+                        R wa = (ma > (R)0) ? J.n : (R)0, wb = (mb > (R)0) ? J.n : (R)0;
+                        if (IMG) {
+                            wa = (ma <= rcm) ? wa : (R)0;
+                            wb = (mb <= rcm) ? wb : (R)0;
                         }
-                        const R d0 = p01 - p00, d1 = p11 - p10;
-                        const R lo = p00 + fS * d0, hi = p10 + fS * d1;
-                        const R gD = hi - lo;
-                        phi = lo + fD * gD;
+                        const R caj = kc.csig * J.a;
+                        R pa, qa = 0, pb, qb = 0, unused;
+                        pair_eval<R, ADJ, false, NSIG>(kc, tab, tabg, ma, Ia.a, Ia.b, J.a, caj, pa, qa, unused);
+                        pair_eval<R, ADJ, false, NSIG>(kc, tab, tabg, mb, Ib.a, Ib.b, J.a, caj, pb, qb, unused);
+                        if (KAHAN) {
+                            R y = wa * pa - cma, t = acca + y;
+                            cma = (t - acca) - y;
+                            acca = t;
+                            y = wb * pb - cmb;
+                            t = accb + y;
+                            cmb = (t - accb) - y;
+                            accb = t;
+                        } else {
+                            acca += wa * pa;
+                            accb += wb * pb;
+                        }
                         if (ADJ) {
-                            const R gS = d0 + fD * (d1 - d0);
-                            // 2 dD dphi/dq_i = gD r + gS (4 csig u a_j / s^2) = gD r + gS u inv inv 4 b_j
-                            dq = gD * r + gS * ((u * inv) * (inv * ((R)4 * J.b)));
+                            accqa += wa * qa;
+                            accqb += wb * qb;
                         }
-                    } else {
-                        const R r6 = r2 * r2 * r2;
-                        const R pp = pi + J.p;
-                        phi = -casym * drcp(r6 * pi * J.p * pp);
-                        if (ADJ) dq = -phi * (c1 + c2 * drcp(pp));
                     }
-                    if (KAHAN) {
-                        R y = w * phi - cmp;
-                        R t = acc + y;
-                        cmp = (t - acc) - y;
-                        acc = t;
-                        if (ADJ) {
-                            R yq = w * dq - cmpq;
-                            R tq = accq + yq;
-                            cmpq = (tq - accq) - yq;
-                            accq = tq;
-                        }
+                    if (home) {
+                        Sc_a += (double)acca - (double)cma;
+                        Sc_b += (double)accb - (double)cmb;
                     } else {
-                        acc += w * phi;
-                        if (ADJ) accq += w * dq;
+                        SL_a += (double)acca - (double)cma;
+                        SL_b += (double)accb - (double)cmb;
+                    }
+                    if (ADJ) {
+                        Sq_a += (double)accqa;
+                        Sq_b += (double)accqb;
                     }
                 }
-                if (home) S0c += (double)acc - (double)cmp;
-                else S0L += (double)acc - (double)cmp;
-                if (ADJ) Sq += (double)accq - (double)cmpq;
+            }
+        } else {
+            // off-diagonal item: both orders of every pair, j tiles rotating through the lanes
+            const int J0 = (I + 1) * kBI + (c - 1) * A.JC, J1 = min(N, J0 + A.JC);
+            for (int t0 = J0; t0 < J1; t0 += 64) {
+                const int jj = t0 + lane;
+                const bool jv = jj < J1;
+                const Rec Jr = P[jv ? jj : J1 - 1];
+                R jSc = 0, jSL = 0, jSq = 0;
+                for (int L = 0; L < nimg; ++L) {
+                    R sxa = Ia.x, sya = Ia.y, sza = Ia.z, sxb = Ib.x, syb = Ib.y, szb = Ib.z;
+                    bool home = true;
+                    if (IMG) {
+                        const R mx = (R)(imgs[4 * L + 0] * sg.nx), my = (R)(imgs[4 * L + 1] * sg.ny),
+                                mz = (R)(imgs[4 * L + 2] * sg.nz);
+                        sxa -= mx;
+                        sya -= my;
+                        sza -= mz;
+                        sxb -= mx;
+                        syb -= my;
+                        szb -= mz;
+                        home = (L == A.home);
+                    }
+                    R xj = Jr.x, yj = Jr.y, zj = Jr.z, aj = Jr.a, nj = jv ? Jr.n : (R)0;
+                    R accj = 0, accqj = 0;
+                    R acca = 0, accqa = 0, accb = 0, accqb = 0, cma = 0, cmb = 0;
+                    for (int st = 0; st < 64; ++st) {
+                        const R ma = dist2<R, CUBIC>(kc, sxa - xj, sya - yj, sza - zj);
+                        const R mb = dist2<R, CUBIC>(kc, sxb - xj, syb - yj, szb - zj);
+                        const R caj = kc.csig * aj;
+                        R pa, qa = 0, ja = 0, pb, qb = 0, jb = 0;
+                        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, ma, Ia.a, Ia.b, aj, caj, pa, qa, ja);
+                        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, mb, Ib.a, Ib.b, aj, caj, pb, qb, jb);
+                        R wja = nj, wjb = nj, wia = nia, wib = nib;
+                        if (IMG) {
+                            wja = (ma <= rcm) ? nj : (R)0;
+                            wjb = (mb <= rcm) ? nj : (R)0;
+                            wia = (ma <= rcm) ? nia : (R)0;
+                            wib = (mb <= rcm) ? nib : (R)0;
+                        }
+                        if (KAHAN) {
+                            R y = wja * pa - cma, t = acca + y;
+                            cma = (t - acca) - y;
+                            acca = t;
+                            y = wjb * pb - cmb;
+                            t = accb + y;
+                            cmb = (t - accb) - y;
+                            accb = t;
+                        } else {
+                            acca = fma(wja, pa, acca);
+                            accb = fma(wjb, pb, accb);
+                        }
+                        accj = fma(wib, pb, fma(wia, pa, accj));
+                        if (ADJ) {
+                            accqa = fma(wja, qa, accqa);
+                            accqb = fma(wjb, qb, accqb);
+                            accqj = fma(wib, jb, fma(wia, ja, accqj));
+                        }
+                        xj = wrot(xj);
+                        yj = wrot(yj);
+                        zj = wrot(zj);
+                        aj = wrot(aj);
+                        nj = wrot(nj);
+                        accj = wrot(accj);
+                        if (ADJ) accqj = wrot(accqj);
+                    }
+                    if (home) {
+                        Sc_a += (double)acca - (double)cma;
+                        Sc_b += (double)accb - (double)cmb;
+                        jSc += accj;
+                    } else {
+                        SL_a += (double)acca - (double)cma;
+                        SL_b += (double)accb - (double)cmb;
+                        jSL += accj;
+                    }
+                    if (ADJ) {
+                        Sq_a += (double)accqa;
+                        Sq_b += (double)accqb;
+                        jSq += accqj;
+                    }
+                }
+                // j-side sums of the tile: 16 wavefronts in a fixed order
+                red[(w * A.NJ + 0) * 64 + lane] = jSc;
+                if (IMG) red[(w * A.NJ + iS0L) * 64 + lane] = jSL;
+                if (ADJ) red[(w * A.NJ + iSq) * 64 + lane] = jSq;
+                __syncthreads();
+                if (threadIdx.x < A.NJ * 64) {
+                    const int a = threadIdx.x >> 6, jl = threadIdx.x & 63;
+                    R sum = 0;
+                    for (int v = 0; v < kWaves; ++v) sum += red[(v * A.NJ + a) * 64 + jl];
+                    if (t0 + jl < J1) jpart[a * A.jstride + slot * A.JC + (t0 + jl - J0)] = sum;
+                }
+                __syncthreads();
             }
         }
-        if (active) {
-            const int64_t slot = sg.part_off + (int64_t)c * N + il;
-            part[slot] = S0c;
-            if (IMG) part[A.part_stride + slot] = S0L;
-            if (ADJ) part[2 * A.part_stride + slot] = Sq / A.dD2;
+        const int64_t base = slot * kBI + w * 128 + lane;
+        const double qscale = sg.hx / A.dD2;  // d/dq = h_x / (2 dD) times the sums above
+        if (acta) {
+            ipart[base] = Sc_a;
+            if (IMG) ipart[iS0L * A.istride + base] = SL_a;
+            if (ADJ) ipart[iSq * A.istride + base] = Sq_a * qscale;
+        }
+        if (actb) {
+            ipart[base + 64] = Sc_b;
+            if (IMG) ipart[iS0L * A.istride + base + 64] = SL_b;
+            if (ADJ) ipart[iSq * A.istride + base + 64] = Sq_b * qscale;
         }
     }
 }
@@ -469,8 +682,12 @@ struct FinArgs {
     const Seg *segs;
     int B;
     const int64_t *hdr;
-    const double *part;
-    int64_t part_stride;
+    const int64_t *rowoff;
+    const double *ipart;
+    const void *jpart;
+    int jfp64;
+    int64_t istride, jstride;
+    int JC, NI, NJ;
     int img, adj, self_term;
     const int32_t *gidx;
     const double *n, *q0, *dqdn;
@@ -511,11 +728,32 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
     if (lp < sg.N) {
         const int64_t p = sg.p_off + lp;
         double S0c = 0.0, S0L = 0.0, Sq = 0.0;
-        for (int c = 0; c < sg.C; ++c) {
-            int64_t slot = sg.part_off + (int64_t)c * sg.N + lp;
-            S0c += F.part[slot];
-            if (F.img) S0L += F.part[F.part_stride + slot];
-            if (F.adj) Sq += F.part[2 * F.part_stride + slot];
+        const int iL = 1, iq = F.NI - 1;
+        const int64_t *ro = F.rowoff + sg.row_base;
+        // as an i-point: the diagonal item and the chunks of its own row block
+        const int64_t Bk = lp / kBI, t = lp - Bk * kBI;
+        for (int64_t it = ro[Bk]; it < ro[Bk + 1]; ++it) {
+            const int64_t k = (sg.slot_base + it) * kBI + t;
+            S0c += F.ipart[k];
+            if (F.img) S0L += F.ipart[iL * F.istride + k];
+            if (F.adj) Sq += F.ipart[iq * F.istride + k];
+        }
+        // as a j-point: one chunk in each earlier row block
+        for (int64_t I = 0; I < Bk; ++I) {
+            const int64_t off = lp - (I + 1) * kBI;
+            const int64_t cc = off / F.JC;
+            const int64_t k = (sg.slot_base + ro[I] + 1 + cc) * F.JC + (off - cc * F.JC);
+            if (F.jfp64) {
+                const double *jp = (const double *)F.jpart;
+                S0c += jp[k];
+                if (F.img) S0L += jp[iL * F.jstride + k];
+                if (F.adj) Sq += jp[iq * F.jstride + k] * (sg.hx / (2.0 * F.dD));
+            } else {
+                const float *jp = (const float *)F.jpart;
+                S0c += (double)jp[k];
+                if (F.img) S0L += (double)jp[iL * F.jstride + k];
+                if (F.adj) Sq += (double)jp[iq * F.jstride + k] * (sg.hx / (2.0 * F.dD));
+            }
         }
         const int64_t g = F.gidx[p];
         const double nn = F.n[g], q = F.q0[g];
@@ -654,8 +892,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmArgs A)
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t hdr, counter, flag, segs, imgs, counts, recs, gidx, part, blockE, res, dEdq, total;
-    int64_t nblocks, part_stride, fin_blocks, Gtot;
+    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, dEdq, total;
+    int64_t nblocks, slots, rows, fin_blocks, Gtot;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -665,28 +903,17 @@ struct Plan {
     std::vector<int> imgs;  // 4 ints per image
     int nimg = 1, home = 0;
     bool img = false;
+    int JC = 8192;
+    int NI = 1, NJ = 1;
     Layout L;
 };
 
-int chunks_for(const GridDev &g, const vdw_opts *o, int cus)
-{
-    if (o->j_chunks > 0) return o->j_chunks;
-    // enough items to keep every CU busy several times over, and items no
-    // longer than ~16k j-terms per i-block
-    int64_t nib = (g.G + kPairThreads - 1) / kPairThreads;
-    int64_t c1 = (8LL * cus + nib - 1) / nib;
-    int64_t c2 = (g.G + 16383) / 16384;
-    int64_t c = c1 > c2 ? c1 : c2;
-    if (c < 1) c = 1;
-    if (c > 64) c = 64;
-    return (int)c;
-}
-
-int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int fp64, int adj, int cus,
-              Plan *P)
+int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int fp64, int adj, Plan *P)
 {
     P->segs.resize(B);
-    int64_t t_off = 0, part = 0, fin = 0, Gtot = 0;
+    P->JC = o->j_chunks > 0 ? 1024 * o->j_chunks : 8192;
+    const int64_t JC = P->JC;
+    int64_t t_off = 0, slots = 0, rows = 0, fin = 0, Gtot = 0;
     for (int b = 0; b < B; ++b) {
         GridDev g;
         int rc = validate_grid(&grids[b], &g);
@@ -712,12 +939,20 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         s.nbx = (g.nx + 3) / 4;
         s.nby = (g.ny + 3) / 4;
         s.nbz = (g.nz + 3) / 4;
-        s.C = chunks_for(g, o, cus);
         int64_t T = (int64_t)s.nbx * s.nby * s.nbz * 64;
         s.T = (T + kCompactBlock - 1) / kCompactBlock * kCompactBlock;
         s.t_off = t_off;
         t_off += s.T;
-        part += (int64_t)s.C * g.G;
+        // work items if every point were kept (an upper bound for any density)
+        int64_t nib = (g.G + kBI - 1) / kBI, items = 0;
+        for (int64_t I = 0; I < nib; ++I) {
+            int64_t rest = g.G - (I + 1) * kBI;
+            items += 1 + (rest > 0 ? (rest + JC - 1) / JC : 0);
+        }
+        s.row_base = rows;
+        rows += nib + 1;
+        s.slot_base = slots;
+        slots += items;
         fin += (g.G + kFinThreads - 1) / kFinThreads;
         Gtot += g.G;
     }
@@ -743,12 +978,15 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             }
     if (P->nimg > 4096) return fail(VDW_EINVAL, "too many images (%d)", P->nimg);
     P->img = P->nimg > 1 || o->r_cut > 0.0;
+    P->NI = P->NJ = 1 + (P->img ? 1 : 0) + (adj ? 1 : 0);
 
     Layout &L = P->L;
     L.nblocks = t_off / kCompactBlock;
-    L.part_stride = part;
+    L.slots = slots;
+    L.rows = rows;
     L.fin_blocks = fin;
     L.Gtot = Gtot;
+    const size_t esz = fp64 ? sizeof(double) : sizeof(float);
     size_t off = 0;
     L.hdr = off;
     off = align256(off + HDR_WORDS * sizeof(int64_t));
@@ -762,12 +1000,16 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     off = align256(off + P->imgs.size() * sizeof(int));
     L.counts = off;
     off = align256(off + (L.nblocks + 1) * sizeof(int64_t));
+    L.rowoff = off;
+    off = align256(off + rows * sizeof(int64_t));
     L.recs = off;
     off = align256(off + Gtot * (fp64 ? sizeof(RecD) : sizeof(RecF)));
     L.gidx = off;
     off = align256(off + Gtot * sizeof(int32_t));
-    L.part = off;
-    off = align256(off + 3 * part * sizeof(double));
+    L.ipart = off;
+    off = align256(off + (size_t)P->NI * slots * kBI * sizeof(double));
+    L.jpart = off;
+    off = align256(off + (size_t)P->NJ * slots * JC * esz);
     L.blockE = off;
     off = align256(off + 3 * fin * sizeof(double));
     L.res = off;
@@ -796,39 +1038,54 @@ int validate_opts(const vdw_opts *o)
 thread_local vdw_stats g_stats;
 thread_local int g_timing = 0;
 
-template <typename R, bool ADJ, bool IMG, bool KAHAN>
-int launch_pair_t(const PairArgs &a, int grid, size_t lds, hipStream_t s)
+struct PairPtrs {
+    const void *recs;
+    const Seg *segs;
+    const int64_t *hdr;
+    int *counter;
+    const void *tabg;
+    const int *imgs;
+    const int64_t *rowoff;
+    double *ipart;
+    void *jpart;
+};
+
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC>
+int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s)
 {
-    auto k = pair_kernel<R, ADJ, IMG, KAHAN>;
+    auto k = pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC>;
     if (lds > 65536) {
         // raises the dynamic-LDS limit where the runtime enforces one; a
         // failure here surfaces at the launch below
         (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kPairThreads), lds, s, a, (const typename RecOf<R>::T *)a.recs, a.segs,
-                       a.hdr, a.counter, (const R *)a.tabg, a.imgs, a.part);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kPairThreads), lds, s, a, (const typename RecOf<R>::T *)p.recs, p.segs,
+                       p.hdr, p.counter, (const R *)p.tabg, p.imgs, p.rowoff, p.ipart, (R *)p.jpart);
     VDW_HIP(hipGetLastError());
     return VDW_OK;
 }
 
-int launch_pair(int fp64, int adj, int img, int kahan, const PairArgs &a, int grid, size_t lds, hipStream_t s)
+// Instantiated variants: FP32C with n_sigma = 64 on cubic or general
+// orthorhombic grids (the fast paths), FP32C for any n_sigma, Kahan-
+// compensated FP32C, and plain FP64; each with and without the adjoint
+// sums and the image loop.
+template <typename R, bool KAHAN, int NSIG, bool CUBIC>
+int launch_pair_v(int adj, int img, const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s)
 {
-    if (fp64) {
-        if (adj) return img ? launch_pair_t<double, true, true, false>(a, grid, lds, s)
-                            : launch_pair_t<double, true, false, false>(a, grid, lds, s);
-        return img ? launch_pair_t<double, false, true, false>(a, grid, lds, s)
-                   : launch_pair_t<double, false, false, false>(a, grid, lds, s);
-    }
-    if (kahan) {
-        if (adj) return img ? launch_pair_t<float, true, true, true>(a, grid, lds, s)
-                            : launch_pair_t<float, true, false, true>(a, grid, lds, s);
-        return img ? launch_pair_t<float, false, true, true>(a, grid, lds, s)
-                   : launch_pair_t<float, false, false, true>(a, grid, lds, s);
-    }
-    if (adj) return img ? launch_pair_t<float, true, true, false>(a, grid, lds, s)
-                        : launch_pair_t<float, true, false, false>(a, grid, lds, s);
-    return img ? launch_pair_t<float, false, true, false>(a, grid, lds, s)
-               : launch_pair_t<float, false, false, false>(a, grid, lds, s);
+    if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s)
+                        : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s);
+    return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s)
+               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s);
+}
+
+int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, const PairArgs &a, const PairPtrs &p,
+                int grid, size_t lds, hipStream_t s)
+{
+    if (fp64) return launch_pair_v<double, false, 0, false>(adj, img, a, p, grid, lds, s);
+    if (kahan) return launch_pair_v<float, true, 0, false>(adj, img, a, p, grid, lds, s);
+    if (nsig == 64) return cubic ? launch_pair_v<float, false, 64, true>(adj, img, a, p, grid, lds, s)
+                                 : launch_pair_v<float, false, 64, false>(adj, img, a, p, grid, lds, s);
+    return launch_pair_v<float, false, 0, false>(adj, img, a, p, grid, lds, s);
 }
 
 // The whole pipeline for B densities.
@@ -852,7 +1109,7 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     rc = device_info(&dev);
     if (rc) return rc;
     Plan P;
-    rc = make_plan(B, grids, grid_off, o, fp64, adj, dev.cus, &P);
+    rc = make_plan(B, grids, grid_off, o, fp64, adj, &P);
     if (rc) return rc;
     if (ws_bytes < P.L.total)
         return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
@@ -866,7 +1123,9 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     int64_t *counts = (int64_t *)(w + L.counts);
     void *recs = w + L.recs;
     int32_t *gidx = (int32_t *)(w + L.gidx);
-    double *part = (double *)(w + L.part);
+    int64_t *rowoff = (int64_t *)(w + L.rowoff);
+    double *ipart = (double *)(w + L.ipart);
+    void *jpart = w + L.jpart;
     double *blockE = (double *)(w + L.blockE);
     double *res = (double *)(w + L.res);
     double *dEdq = (double *)(w + L.dEdq);
@@ -887,7 +1146,8 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     // compaction
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)L.nblocks), dim3(kCompactThreads), 0, s, (const Seg *)segs, B,
                        n_d, o->n_cut, counts, flag);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, L.nblocks, segs, B, hdr);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, L.nblocks, segs, B, hdr, rowoff,
+                       (int64_t)P.JC);
     ScatterArgs sa;
     sa.segs = segs;
     sa.B = B;
@@ -907,41 +1167,54 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     // pair kernel
     const size_t esz = fp64 ? sizeof(double) : sizeof(float);
     const int S = tp->n_sigma + 1;
-    const size_t lds_cap = dev.lds_per_block > 1024 ? dev.lds_per_block - 1024 : 0;
+    const size_t red_bytes = (size_t)kWaves * P.NJ * 64 * esz;  // j-side tile sums
+    const size_t lds_cap = dev.lds_per_block > 256 + red_bytes ? dev.lds_per_block - 256 - red_bytes : 0;
     int K = (int)(lds_cap / (S * esz));
     if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
     if (K > tp->n_D) K = tp->n_D;
     if (K < 2) K = 2;  // the kernel reads a clamped LDS row unconditionally
     PairArgs pa;
-    pa.recs = recs;
-    pa.segs = segs;
     pa.B = B;
-    pa.hdr = hdr;
-    pa.counter = counter;
-    pa.tabg = fp64 ? (const void *)phi_d : (const void *)phi_f;
     pa.nD = tp->n_D;
     pa.nS = tp->n_sigma;
     pa.S = S;
     pa.K = K;
+    pa.JC = P.JC;
+    pa.csig = sqrt((double)(tp->n_sigma - 1));
     pa.tDmax = (double)(tp->n_D - 1);
     pa.tSclamp = fp64 ? nextafter((double)(tp->n_sigma - 1), 0.0) : (double)nextafterf((float)(tp->n_sigma - 1), 0.0f);
-    pa.casym = 12.0 * pow(4.0 * 3.14159265358979323846 / 9.0, 3);
+    const double Casym = 12.0 * pow(4.0 * 3.14159265358979323846 / 9.0, 3);
+    pa.casym = Casym / pow(2.0 * dD, 6);  // the asymptote in units of h_x and a = q h_x / (2 dD)
     pa.dD2 = 2.0 * dD;
     pa.rc2 = o->r_cut > 0.0 ? o->r_cut * o->r_cut : INFINITY;
-    pa.imgs = imgs;
     pa.nimg = P.nimg;
     pa.home = P.home;
-    pa.part = part;
-    pa.part_stride = L.part_stride;
+    pa.NI = P.NI;
+    pa.NJ = P.NJ;
+    pa.istride = L.slots * kBI;
+    pa.jstride = L.slots * (int64_t)P.JC;
+    PairPtrs pp;
+    pp.recs = recs;
+    pp.segs = segs;
+    pp.hdr = hdr;
+    pp.counter = counter;
+    pp.tabg = fp64 ? (const void *)phi_d : (const void *)phi_f;
+    pp.imgs = imgs;
+    pp.rowoff = rowoff;
+    pp.ipart = ipart;
+    pp.jpart = jpart;
     int grid = o->grid_blocks > 0 ? o->grid_blocks : dev.cus;
-    size_t lds = (size_t)K * S * esz;
+    size_t lds = (size_t)K * S * esz + red_bytes + 16;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (g_timing) {
         VDW_HIP(hipEventCreate(&ev0));
         VDW_HIP(hipEventCreate(&ev1));
         VDW_HIP(hipEventRecord(ev0, s));
     }
-    rc = launch_pair(fp64, adj, P.img ? 1 : 0, o->kahan, pa, grid, lds, s);
+    int cubic = 1;
+    for (int b = 0; b < B; ++b)
+        if (!(P.segs[b].hx == P.segs[b].hy && P.segs[b].hx == P.segs[b].hz)) cubic = 0;
+    rc = launch_pair(fp64, adj, P.img ? 1 : 0, o->kahan, tp->n_sigma, cubic, pa, pp, grid, lds, s);
     if (rc) return rc;
     if (g_timing) VDW_HIP(hipEventRecord(ev1, s));
 
@@ -950,8 +1223,15 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     fa.segs = segs;
     fa.B = B;
     fa.hdr = hdr;
-    fa.part = part;
-    fa.part_stride = L.part_stride;
+    fa.rowoff = rowoff;
+    fa.ipart = ipart;
+    fa.jpart = jpart;
+    fa.jfp64 = fp64;
+    fa.istride = pa.istride;
+    fa.jstride = pa.jstride;
+    fa.JC = P.JC;
+    fa.NI = P.NI;
+    fa.NJ = P.NJ;
     fa.img = P.img ? 1 : 0;
     fa.adj = adj;
     fa.self_term = o->self_term;
@@ -964,7 +1244,7 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     fa.nS = tp->n_sigma;
     fa.dD = dD;
     fa.Dmax = tp->D_max;
-    fa.casym = pa.casym;
+    fa.casym = Casym;
     fa.blockE = blockE;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
@@ -1010,7 +1290,7 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     g_stats.pair_kernel_ms = ms;
     g_stats.lds_rows = K;
     g_stats.block_threads = kPairThreads;
-    g_stats.j_chunks = P.segs[0].C;
+    g_stats.j_chunks = P.JC / 1024;
     g_stats.grid_blocks = grid;
     return VDW_OK;
 }
@@ -1030,11 +1310,8 @@ extern "C" size_t enl_batched_workspace_size(int32_t B, const vdw_grid *grids, c
                                              const vdw_opts *opts)
 {
     if (B < 1 || !grids || validate_opts(opts) || validate_table(tp)) return 0;
-    DevInfo dev;
-    int cus = 256;
-    if (device_info(&dev) == VDW_OK) cus = dev.cus;
     Plan P;
-    if (make_plan(B, grids, nullptr, opts, opts->precision == VDW_FP64, 1, cus, &P)) return 0;
+    if (make_plan(B, grids, nullptr, opts, opts->precision == VDW_FP64, 1, &P)) return 0;
     return P.L.total;
 }
 
