@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 # fused energy + adjoint, table branch, one evaluation for both orders of a pair
 FLOP_PER_UNORDERED_PAIR = 45
+FLOP_PER_UNORDERED_PAIR_ENERGY = 30
 PEAK_FP32_TFLOPS = 157.3
 
 
@@ -37,6 +38,8 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--R", type=float, default=7.0)
+    p.add_argument("--workload", default="kr", choices=["kr", "slab", "batch", "dimer24"],
+                   help="kr: the Kr2-like dimer (the reported metric); slab, batch, dimer24: the other cases")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0, help="oracle rows in the CPU sample (0: auto)")
@@ -68,21 +71,45 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    wl = W.kr_dimer(a.R)
-    tparams = V.TableParams(n_D=2048, n_sigma=64, D_max=48.0)
+    if a.workload == "kr":
+        wls = [W.kr_dimer(a.R)]
+        desc = (f"Kr2-like dimer, 96^3 grid h=0.25 bohr, R={a.R:g} bohr, n_cut=1e-5, "
+                f"table 2048x64 on D<=48, energy + potential fused")
+    elif a.workload == "slab":
+        wls = [W.xe_slab()]
+        desc = ("Xe-like slab, 48x48x224 grid of an 8.6x8.6x40 bohr cell, periodic x,y, images |m|,|p|<=3, "
+                "r<=30 bohr, n_cut=1e-5, table 2048x64, energy + potential fused")
+    elif a.workload == "batch":
+        wls = W.molecule_batch(64)
+        desc = "64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched call"
+    else:
+        wls = [W.dimer_small()]
+        desc = "dimer 24^3 grid h=0.5 bohr, n_cut=1e-6, table 1024x32, energy only"
+    wl = wls[0]
+    tparams = V.TableParams(n_D=1024, n_sigma=32, D_max=48.0) if a.workload == "dimer24" else \
+        V.TableParams(n_D=2048, n_sigma=64, D_max=48.0)
     print(f"# building table {tparams.n_D}x{tparams.n_sigma} on the GPU", file=sys.stderr, flush=True)
     t0 = time.time()
     table = V.build_phi_table(tparams, device=dev)
     torch.cuda.synchronize()
     t_table = time.time() - t0
-    g = V.Grid(wl.n, wl.h, wl.periodic)
-    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device=dev)
+    grids = [V.Grid(w.n, w.h, w.periodic) for w in wls]
+    ns = [torch.tensor(w.rho.reshape(-1), dtype=torch.float64, device=dev) for w in wls]
+    n, offs = V.pack_batch(grids, ns)
+    g = grids[0]
 
     def opts(prec):
-        return V.Opts(n_cut=wl.n_cut, precision=prec, kahan=a.kahan, table_lds_rows=a.lds_rows,
-                      j_chunks=a.j_chunks, grid_blocks=a.grid_blocks)
+        return V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec, kahan=a.kahan,
+                      table_lds_rows=a.lds_rows, j_chunks=a.j_chunks, grid_blocks=a.grid_blocks)
 
     def step(prec):
+        if a.workload == "batch":
+            qd = V.compute_q0_batched(grids, n, offs, wl.n_cut)
+            E, v = V.enl_potential_batched(grids, n, offs, qd, table, opts(prec))
+            return tuple(sum(e[k] for e in E) for k in range(3)), v
+        if a.workload == "dimer24":
+            qd = V.compute_q0(g, n, wl.n_cut, derivatives=False)
+            return V.enl_energy(g, n, qd["q0"], table, opts(prec)), n
         qd = V.compute_q0(g, n, wl.n_cut)
         return V.enl_potential(g, n, qd, table, opts(prec))
 
@@ -104,7 +131,8 @@ def main():
         print(f"# timed {steps} steps precision={prec}: {dt:.3f} s", file=sys.stderr, flush=True)
         return dt, E, v, float(np.mean(kms)), V.last_stats()
 
-    dt, E32, v32, kms32, st = timed(V.VDW_FP32C, a.steps, a.warmup)
+    main_prec = V.VDW_FP64 if a.workload == "dimer24" else V.VDW_FP32C
+    dt, E32, v32, kms32, st = timed(main_prec, a.steps, a.warmup)
     pairs = st["pairs"]
     value = pairs * a.steps / dt
     out = {
@@ -118,11 +146,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if a.workload == "dimer24" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"Kr2-like dimer, 96^3 grid h=0.25 bohr, R={a.R:g} bohr, n_cut=1e-5, "
-                        f"table 2048x64 on D<=48, energy + potential fused",
+            "workload": desc,
             "retained_points": st["retained"],
             "pairs_per_step": pairs,
             "lds_rows": st["lds_rows"],
@@ -131,7 +158,8 @@ def main():
             "kahan": a.kahan,
         },
     }
-    achieved = 0.5 * pairs * FLOP_PER_UNORDERED_PAIR / (kms32 * 1e-3) / 1e12
+    fpp = FLOP_PER_UNORDERED_PAIR_ENERGY if a.workload == "dimer24" else FLOP_PER_UNORDERED_PAIR
+    achieved = 0.5 * pairs * fpp / (kms32 * 1e-3) / 1e12
     out["roofline"] = {
         "bound": "alu",
         "achieved": achieved,
@@ -139,13 +167,15 @@ def main():
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_TFLOPS,
         "traffic": None,
-        "kernel": "pair_kernel<float, ADJ, noIMG>",
+        "kernel": "pair_kernel<%s, %s, %s>" % ("double" if a.workload == "dimer24" else "float",
+                                                "energy" if a.workload == "dimer24" else "ADJ",
+                                                "IMG" if a.workload == "slab" else "noIMG"),
         "kernel_ms": kms32,
-        "flop_per_unordered_pair": FLOP_PER_UNORDERED_PAIR,
+        "flop_per_unordered_pair": fpp,
     }
     out["energy_ha"] = {"E_pair0": E32[0], "E_pairL": E32[1], "E_self": E32[2], "E": sum(E32)}
     out["table_build_s"] = t_table
-    if not a.no_fp64:
+    if not a.no_fp64 and a.workload != "dimer24":
         steps64 = max(1, a.steps // 2)
         dt64, E64, v64, kms64, _ = timed(V.VDW_FP64, steps64, 1)
         rate64 = pairs * steps64 / dt64
@@ -154,7 +184,7 @@ def main():
         out["fp64"] = {"value": rate64, "ms_per_step": 1e3 * dt64 / steps64, "kernel_ms": kms64,
                        "speedup_fp32c_over_fp64": value / rate64,
                        "fp32c_vs_fp64": {"dE_rel": dE, "dv_rel_l2": dv}}
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.workload == "kr":
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)
     print(json.dumps(out), flush=True)
 

@@ -423,6 +423,115 @@ __device__ __forceinline__ void pair_eval(const PairK<R> &k, const R *tab, const
     }
 }
 
+// One 64-step ring of an off-diagonal tile against one image shift: every
+// lane meets every j of the tile; the j values and the j-side sums rotate
+// with the records.  MASK applies the distance cut pair by pair (only for
+// tiles that straddle it).
+// Kahan-compensated sum step: s + y with the running error in c.
+template <typename R>
+__device__ __forceinline__ void kadd(R &sum, R &c, R y)
+{
+    const R t0 = y - c, t1 = sum + t0;
+    c = (t1 - sum) - t0;
+    sum = t1;
+}
+
+template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, bool CUBIC>
+__device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm, R sxa,
+                                       R sya, R sza, R aia, R bia, R nia, R sxb, R syb, R szb, R aib, R bib, R nib,
+                                       R xj, R yj, R zj, R aj, R nj, R &acca, R &accqa, R &accb, R &accqb, R &accj,
+                                       R &accqj)
+{
+    R ca = 0, cqa = 0, cb = 0, cqb = 0, cj = 0, cqj = 0;  // Kahan terms (KAHAN only)
+    for (int st = 0; st < 64; ++st) {
+        const R ma = dist2<R, CUBIC>(kc, sxa - xj, sya - yj, sza - zj);
+        const R mb = dist2<R, CUBIC>(kc, sxb - xj, syb - yj, szb - zj);
+        const R caj = kc.csig * aj;
+        R pa, qa = 0, ja = 0, pb, qb = 0, jb = 0;
+        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, ma, aia, bia, aj, caj, pa, qa, ja);
+        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, mb, aib, bib, aj, caj, pb, qb, jb);
+        R wja = nj, wjb = nj, wia = nia, wib = nib;
+        if (MASK) {
+            wja = (ma <= rcm) ? nj : (R)0;
+            wjb = (mb <= rcm) ? nj : (R)0;
+            wia = (ma <= rcm) ? nia : (R)0;
+            wib = (mb <= rcm) ? nib : (R)0;
+        }
+        if (KAHAN) {
+            kadd(acca, ca, wja * pa);
+            kadd(accb, cb, wjb * pb);
+            kadd(accj, cj, fma(wib, pb, wia * pa));
+            if (ADJ) {
+                kadd(accqa, cqa, wja * qa);
+                kadd(accqb, cqb, wjb * qb);
+                kadd(accqj, cqj, fma(wib, jb, wia * ja));
+            }
+        } else {
+            acca = fma(wja, pa, acca);
+            accb = fma(wjb, pb, accb);
+            accj = fma(wib, pb, fma(wia, pa, accj));
+            if (ADJ) {
+                accqa = fma(wja, qa, accqa);
+                accqb = fma(wjb, qb, accqb);
+                accqj = fma(wib, jb, fma(wia, ja, accqj));
+            }
+        }
+        xj = wrot(xj);
+        yj = wrot(yj);
+        zj = wrot(zj);
+        aj = wrot(aj);
+        nj = wrot(nj);
+        accj = wrot(accj);
+        if (ADJ) accqj = wrot(accqj);
+        if (KAHAN) {
+            cj = wrot(cj);
+            if (ADJ) cqj = wrot(cqj);
+        }
+    }
+    if (KAHAN) {
+        // fold the compensation into the sums
+        acca -= ca;
+        accb -= cb;
+        accj -= cj;
+        accqa -= cqa;
+        accqb -= cqb;
+        accqj -= cqj;
+    }
+}
+
+// Wavefront-wide min / max (every lane gets the result).
+template <typename R>
+__device__ inline R wave_min(R v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (R)__shfl_xor(v, o));
+    return v;
+}
+template <typename R>
+__device__ inline R wave_max(R v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (R)__shfl_xor(v, o));
+    return v;
+}
+
+// Smallest and largest squared distance (units of h_x^2) between two boxes
+// whose x, y, z ranges are given, after shifting the second by (sx, sy, sz).
+template <typename R>
+__device__ inline void box_dist2(const R *bi, const R *bj, R sx, R sy, R sz, R wy, R wz, R &dmin2, R &dmax2)
+{
+    const R sh[3] = {sx, sy, sz};
+    const R wt[3] = {(R)1, wy, wz};
+    dmin2 = 0;
+    dmax2 = 0;
+    for (int a = 0; a < 3; ++a) {
+        // i range [bi[2a], bi[2a+1]], shifted j range [bj[2a] + s, bj[2a+1] + s]
+        const R lo = bj[2 * a] + sh[a], hi = bj[2 * a + 1] + sh[a];
+        const R gap = max((R)0, max(bi[2 * a] - hi, lo - bi[2 * a + 1]));
+        const R far = max(bi[2 * a + 1] - lo, hi - bi[2 * a]);
+        dmin2 += wt[a] * gap * gap;
+        dmax2 += wt[a] * far * far;
+    }
+}
+
 // Pointers are separate __restrict__ parameters so the compiler knows the
 // records, segments and table are not written during the kernel and can
 // fetch wave-uniform records with scalar loads.
@@ -568,14 +677,34 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
         } else {
             // off-diagonal item: both orders of every pair, j tiles rotating through the lanes
             const int J0 = (I + 1) * kBI + (c - 1) * A.JC, J1 = min(N, J0 + A.JC);
+            const bool prune = IMG && A.rc2 < 1e300;
+            R ib[6] = {0, 0, 0, 0, 0, 0};
+            if (prune) {
+                // bounding box of this wavefront's i-points (both per lane)
+                ib[0] = __builtin_amdgcn_readfirstlane(wave_min<R>(min(Ia.x, Ib.x)));
+                ib[1] = __builtin_amdgcn_readfirstlane(wave_max<R>(max(Ia.x, Ib.x)));
+                ib[2] = __builtin_amdgcn_readfirstlane(wave_min<R>(min(Ia.y, Ib.y)));
+                ib[3] = __builtin_amdgcn_readfirstlane(wave_max<R>(max(Ia.y, Ib.y)));
+                ib[4] = __builtin_amdgcn_readfirstlane(wave_min<R>(min(Ia.z, Ib.z)));
+                ib[5] = __builtin_amdgcn_readfirstlane(wave_max<R>(max(Ia.z, Ib.z)));
+            }
             for (int t0 = J0; t0 < J1; t0 += 64) {
                 const int jj = t0 + lane;
                 const bool jv = jj < J1;
                 const Rec Jr = P[jv ? jj : J1 - 1];
+                R jb6[6] = {0, 0, 0, 0, 0, 0};
+                if (prune) {
+                    jb6[0] = __builtin_amdgcn_readfirstlane(wave_min<R>(Jr.x));
+                    jb6[1] = __builtin_amdgcn_readfirstlane(wave_max<R>(Jr.x));
+                    jb6[2] = __builtin_amdgcn_readfirstlane(wave_min<R>(Jr.y));
+                    jb6[3] = __builtin_amdgcn_readfirstlane(wave_max<R>(Jr.y));
+                    jb6[4] = __builtin_amdgcn_readfirstlane(wave_min<R>(Jr.z));
+                    jb6[5] = __builtin_amdgcn_readfirstlane(wave_max<R>(Jr.z));
+                }
                 R jSc = 0, jSL = 0, jSq = 0;
                 for (int L = 0; L < nimg; ++L) {
                     R sxa = Ia.x, sya = Ia.y, sza = Ia.z, sxb = Ib.x, syb = Ib.y, szb = Ib.z;
-                    bool home = true;
+                    bool home = true, masked = IMG;
                     if (IMG) {
                         const R mx = (R)(imgs[4 * L + 0] * sg.nx), my = (R)(imgs[4 * L + 1] * sg.ny),
                                 mz = (R)(imgs[4 * L + 2] * sg.nz);
@@ -586,57 +715,31 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                         syb -= my;
                         szb -= mz;
                         home = (L == A.home);
+                        if (prune) {
+                            // r_i - r_j - L: the j box shifted by +L against the i box
+                            R dmin2, dmax2;
+                            box_dist2<R>(ib, jb6, mx, my, mz, kc.wy, kc.wz, dmin2, dmax2);
+                            if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
+                            masked = dmax2 > rcm;
+                        }
                     }
-                    R xj = Jr.x, yj = Jr.y, zj = Jr.z, aj = Jr.a, nj = jv ? Jr.n : (R)0;
-                    R accj = 0, accqj = 0;
-                    R acca = 0, accqa = 0, accb = 0, accqb = 0, cma = 0, cmb = 0;
-                    for (int st = 0; st < 64; ++st) {
-                        const R ma = dist2<R, CUBIC>(kc, sxa - xj, sya - yj, sza - zj);
-                        const R mb = dist2<R, CUBIC>(kc, sxb - xj, syb - yj, szb - zj);
-                        const R caj = kc.csig * aj;
-                        R pa, qa = 0, ja = 0, pb, qb = 0, jb = 0;
-                        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, ma, Ia.a, Ia.b, aj, caj, pa, qa, ja);
-                        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, mb, Ib.a, Ib.b, aj, caj, pb, qb, jb);
-                        R wja = nj, wjb = nj, wia = nia, wib = nib;
-                        if (IMG) {
-                            wja = (ma <= rcm) ? nj : (R)0;
-                            wjb = (mb <= rcm) ? nj : (R)0;
-                            wia = (ma <= rcm) ? nia : (R)0;
-                            wib = (mb <= rcm) ? nib : (R)0;
-                        }
-                        if (KAHAN) {
-                            R y = wja * pa - cma, t = acca + y;
-                            cma = (t - acca) - y;
-                            acca = t;
-                            y = wjb * pb - cmb;
-                            t = accb + y;
-                            cmb = (t - accb) - y;
-                            accb = t;
-                        } else {
-                            acca = fma(wja, pa, acca);
-                            accb = fma(wjb, pb, accb);
-                        }
-                        accj = fma(wib, pb, fma(wia, pa, accj));
-                        if (ADJ) {
-                            accqa = fma(wja, qa, accqa);
-                            accqb = fma(wjb, qb, accqb);
-                            accqj = fma(wib, jb, fma(wia, ja, accqj));
-                        }
-                        xj = wrot(xj);
-                        yj = wrot(yj);
-                        zj = wrot(zj);
-                        aj = wrot(aj);
-                        nj = wrot(nj);
-                        accj = wrot(accj);
-                        if (ADJ) accqj = wrot(accqj);
-                    }
+                    R accj = 0, accqj = 0, acca = 0, accqa = 0, accb = 0, accqb = 0;
+                    const R nj0 = jv ? Jr.n : (R)0;
+                    if (masked)
+                        ring64<R, ADJ, true, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, Ia.b, nia, sxb, syb,
+                                                          szb, Ib.a, Ib.b, nib, Jr.x, Jr.y, Jr.z, Jr.a, nj0, acca,
+                                                          accqa, accb, accqb, accj, accqj);
+                    else
+                        ring64<R, ADJ, false, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, Ia.b, nia, sxb,
+                                                           syb, szb, Ib.a, Ib.b, nib, Jr.x, Jr.y, Jr.z, Jr.a, nj0, acca,
+                                                           accqa, accb, accqb, accj, accqj);
                     if (home) {
-                        Sc_a += (double)acca - (double)cma;
-                        Sc_b += (double)accb - (double)cmb;
+                        Sc_a += (double)acca;
+                        Sc_b += (double)accb;
                         jSc += accj;
                     } else {
-                        SL_a += (double)acca - (double)cma;
-                        SL_b += (double)accb - (double)cmb;
+                        SL_a += (double)acca;
+                        SL_b += (double)accb;
                         jSL += accj;
                     }
                     if (ADJ) {

@@ -1,0 +1,209 @@
+"""GPU parity at the full workload sizes, in the launch configuration that
+bench.py times, on outputs the oracle can compute one by one: dE/dn at
+sampled grid points (kept points and dropped points next to kept ones),
+each from the oracle rows it needs over all ~6e5 points.  Energies at full
+size are checked through properties (FP32C against FP64, energy-only against
+the fused kernel), since the oracle's full double sum takes minutes there.
+
+The kernel table passed to both sides is built by the oracle (a coarser
+quadrature rule, which changes the table values, not the pair arithmetic).
+"""
+import numpy as np
+import pytest
+
+import vdw_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CHEAP_RULE = dict(gl_points=6, graded_levels=8, kappa=2.0, A0=20.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0810_2273_amd as V
+
+    return V
+
+
+@pytest.fixture(scope="module")
+def big(oracle):
+    tp = oracle.table_params(n_D=2048, n_sigma=64, D_max=48.0, **CHEAP_RULE)
+    return tp, oracle.build_table(tp)
+
+
+def _gpu_table(V, tp, tab):
+    import torch
+
+    params = V.TableParams(n_D=tp.n_D, n_sigma=tp.n_sigma, D_max=tp.D_max, gl_points=tp.gl_points,
+                           graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0)
+    t64 = torch.tensor(tab, dtype=torch.float64, device="cuda:0").contiguous()
+    return V.Table(params, t64, t64.float().contiguous())
+
+
+def _samples(wl, oracle, count, seed):
+    """Kept points (uniform), the densest points, and dropped points whose
+    stencil touches kept ones."""
+    rng = np.random.default_rng(seed)
+    rho = wl.rho.reshape(-1)
+    keep = np.flatnonzero(rho >= wl.n_cut)
+    ks = list(rng.choice(keep, count, replace=False))
+    ks += list(np.argsort(rho)[-4:])
+    g = oracle.Grid(wl.n, wl.h, wl.periodic)
+    Gx = oracle.gradient_operators(g)[0].tocsc()
+    dropped = np.flatnonzero(rho < wl.n_cut)
+    near = [int(k) for k in rng.permutation(dropped)[:20000] if np.any(rho[Gx.getcol(int(k)).indices] >= wl.n_cut)]
+    ks += near[:6]
+    return np.array(sorted(set(int(k) for k in ks)))
+
+
+def _sampled_check(V, oracle, wl, tp, tab, ks, prec, vtol):
+    import torch
+
+    g = V.Grid(wl.n, wl.h, wl.periodic)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    opts = V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec)
+    E, v = V.enl_potential(g, n, qd, _gpu_table(V, tp, tab), opts)
+    v = v.cpu().numpy()
+    say(f"  GPU E = {sum(E):.12e}  ({V.last_stats()['retained']} kept points)")
+    ref = oracle.potential_at(oracle.Grid(wl.n, wl.h, wl.periodic), wl.rho, ks, tab, tp, wl.n_cut, wl.image_max,
+                              wl.r_cut)
+    rel = np.linalg.norm(v[ks] - ref) / np.linalg.norm(ref)
+    say(f"  sampled |dv|/|v| over {len(ks)} points = {rel:.3e}")
+    assert rel <= vtol
+    return E, v
+
+
+@pytest.mark.parametrize("prec,vtol", [(1, 1e-4), (0, 1e-10)])
+def test_kr_dimer_full_size_sampled_potential(V, oracle, big, prec, vtol):
+    """96^3 Kr2-like dimer, R = 7 bohr (576 596 kept points), bench launch
+    configuration; FP32C and FP64."""
+    tp, tab = big
+    wl = W.kr_dimer(7.0)
+    say(f"kr dimer 96^3 precision={prec}")
+    ks = _samples(wl, oracle, 36, seed=7)
+    _sampled_check(V, oracle, wl, tp, tab, ks, prec, vtol)
+
+
+def test_kr_dimer_full_size_energy_properties(V, big):
+    """Full-size energies: FP32C within 1e-6 of FP64 (and v within 1e-4), the
+    energy-only kernel equal to the fused one, and the R-scan binding curve
+    negative at large R with the expected -C6/R^6-like decay."""
+    import torch
+
+    tp, tab = big
+    table = _gpu_table(V, tp, tab)
+    wl = W.kr_dimer(7.0)
+    g = V.Grid(wl.n, wl.h)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    out = {}
+    for prec in (0, 1):
+        say(f"kr dimer energies precision={prec}")
+        out[prec] = V.enl_potential(g, n, qd, table, V.Opts(n_cut=wl.n_cut, precision=prec))
+        Ee = V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, precision=prec))
+        assert sum(Ee) == pytest.approx(sum(out[prec][0]), rel=1e-12 if prec == 0 else 1e-7)
+    e64, e32 = sum(out[0][0]), sum(out[1][0])
+    v64, v32 = out[0][1], out[1][1]
+    dv = float(torch.linalg.norm(v32 - v64) / torch.linalg.norm(v64))
+    say(f"  E64={e64:.12e} E32={e32:.12e} rel={abs(e32 - e64) / abs(e64):.2e} dv={dv:.2e}")
+    assert abs(e32 - e64) <= 1e-6 * abs(e64)
+    assert dv <= 1e-4
+
+
+def test_binding_curve_tail(V, big):
+    """E_nl(R) - E(A) - E(B) on the 96^3 dimer for R in {10, 14}: negative
+    (attractive), and shrinking with R (the nonlocal term's -C6/R^6 tail)."""
+    import torch
+
+    tp, tab = big
+    table = _gpu_table(V, tp, tab)
+    dE = {}
+    for R in (10.0, 14.0):
+        es = {}
+        for which in ("both", "A", "B"):
+            wl = W.kr_dimer(R, which=which)
+            g = V.Grid(wl.n, wl.h)
+            n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+            qd = V.compute_q0(g, n, wl.n_cut)
+            es[which] = sum(V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, precision=1)))
+        dE[R] = es["both"] - es["A"] - es["B"]
+        say(f"  R={R}: dE = {dE[R]:.6e} Ha")
+    assert dE[10.0] < 0 and dE[14.0] < 0 and abs(dE[14.0]) < abs(dE[10.0])
+
+
+@pytest.mark.parametrize("prec,vtol", [(1, 1e-4), (0, 1e-10)])
+def test_xe_slab_full_size_sampled_potential(V, oracle, big, prec, vtol):
+    """48 x 48 x 224 Xe-like slab, periodic in x, y, images |m|, |p| <= 3 and the
+    30 bohr cut (351 774 kept points); FP32C and FP64."""
+    tp, tab = big
+    wl = W.xe_slab()
+    say(f"xe slab full size precision={prec}")
+    ks = _samples(wl, oracle, 24, seed=3)
+    E, v = _sampled_check(V, oracle, wl, tp, tab, ks, prec, vtol)
+    assert E[1] < 0  # the images attract
+
+
+def _batch(V, mols):
+    import torch
+
+    grids = [V.Grid(m.n, m.h, m.periodic) for m in mols]
+    ns = [torch.tensor(m.rho.reshape(-1), dtype=torch.float64, device="cuda:0") for m in mols]
+    n, offs = V.pack_batch(grids, ns)
+    qd = V.compute_q0_batched(grids, n, offs, mols[0].n_cut)
+    return grids, ns, n, offs, qd
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_batch_matches_single_calls(V, big, prec):
+    """64 molecule densities of 16^3..64^3 points in one batched call equal 64
+    separate calls (the same kernels on a different work list)."""
+    import torch
+
+    tp, tab = big
+    table = _gpu_table(V, tp, tab)
+    mols = W.molecule_batch(64)
+    grids, ns, n, offs, qd = _batch(V, mols)
+    opts = V.Opts(n_cut=mols[0].n_cut, precision=prec)
+    say(f"batch of {len(mols)} (total {offs[-1]} grid points) precision={prec}")
+    Eb, vb = V.enl_potential_batched(grids, n, offs, qd, table, opts)
+    for b in range(len(mols)):
+        q1 = V.compute_q0(grids[b], ns[b], mols[b].n_cut)
+        E1, v1 = V.enl_potential(grids[b], ns[b], q1, table, opts)
+        assert sum(Eb[b]) == pytest.approx(sum(E1), rel=1e-13 if prec == 0 else 1e-9), b
+        seg = vb[offs[b]:offs[b + 1]]
+        assert float(torch.linalg.norm(seg - v1) / torch.linalg.norm(v1)) <= (1e-13 if prec == 0 else 1e-8), b
+
+
+def test_batch_matches_oracle(V, oracle, big):
+    """The batched call against the oracle: full energy and potential for the
+    three smallest molecules, sampled potential for the largest."""
+    tp, tab = big
+    table = _gpu_table(V, tp, tab)
+    mols = W.molecule_batch(64)
+    grids, ns, n, offs, qd = _batch(V, mols)
+    for prec, etol, vtol in ((0, 1e-12, 1e-10), (1, 1e-6, 1e-4)):
+        say(f"batch vs oracle precision={prec}")
+        Eb, vb = V.enl_potential_batched(grids, n, offs, qd, table, V.Opts(n_cut=mols[0].n_cut, precision=prec))
+        vb = vb.cpu().numpy()
+        order = np.argsort([m.G for m in mols])
+        for b in list(order[:3]):
+            m = mols[b]
+            ref = oracle.evaluate(oracle.Grid(m.n, m.h), m.rho, tab, tp, m.n_cut, potential=True)
+            assert abs(sum(Eb[b]) - ref.E) <= etol * abs(ref.E), (b, sum(Eb[b]), ref.E)
+            v = vb[offs[b]:offs[b + 1]]
+            assert np.linalg.norm(v - ref.dEdn) <= vtol * np.linalg.norm(ref.dEdn), b
+        b = int(order[-1])
+        m = mols[b]
+        ks = _samples(m, oracle, 24, seed=11)
+        ref = oracle.potential_at(oracle.Grid(m.n, m.h), m.rho, ks, tab, tp, m.n_cut)
+        v = vb[offs[b]:offs[b + 1]][ks]
+        assert np.linalg.norm(v - ref) <= vtol * np.linalg.norm(ref), b
