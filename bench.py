@@ -30,6 +30,10 @@ if ROOT not in sys.path:
 FLOP_PER_UNORDERED_PAIR = 45
 FLOP_PER_UNORDERED_PAIR_ENERGY = 30
 PEAK_FP32_TFLOPS = 157.3
+# HBM bytes per pair-kernel launch on the Kr2-like dimer, from rocprofv3
+# FETCH_SIZE (x 2.0, the factor a plain 512 MiB copy needs) + WRITE_SIZE of the
+# current kernel (profiles/pair_kernel_kr_dimer96_fp32c.md); None elsewhere.
+TRAFFIC_BYTES = {"kr": (1039380.375 * 2.0 + 961572.15625) * 1024}
 
 
 def parse():
@@ -166,7 +170,7 @@ def main():
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_TFLOPS,
-        "traffic": None,
+        "traffic": TRAFFIC_BYTES.get(a.workload) if a.R == 7.0 else None,
         "kernel": "pair_kernel<%s, %s, %s>" % ("double" if a.workload == "dimer24" else "float",
                                                 "energy" if a.workload == "dimer24" else "ADJ",
                                                 "IMG" if a.workload == "slab" else "noIMG"),

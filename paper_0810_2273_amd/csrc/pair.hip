@@ -349,7 +349,12 @@ struct PairK {
     int S, nS, K;
 };
 
-__device__ inline float dmin(float a, float b) { return __builtin_fminf(a, b); }
+// min of two non-negative values; for FP32 an integer min on the bit
+// patterns (same order for non-negative floats, no NaN quieting needed)
+__device__ inline float dmin(float a, float b)
+{
+    return __builtin_bit_cast(float, min(__builtin_bit_cast(int, a), __builtin_bit_cast(int, b)));
+}
 __device__ inline double dmin(double a, double b) { return __builtin_fmin(a, b); }
 
 // Squared distance in units of h_x^2 from exact integer grid deltas
@@ -385,8 +390,9 @@ __device__ __forceinline__ void pair_eval(const PairK<R> &k, const R *tab, const
         // rows below K come from LDS; the clamped LDS read is always in
         // bounds and is replaced for rows >= K - 1
         const int kl = min(kk, k.K - 2);
-        const int o = (int)__umul24((unsigned)kl, (unsigned)S) + l;
-        R p00 = tab[o], p01 = tab[o + 1], p10 = tab[o + S], p11 = tab[o + S + 1];
+        const unsigned ob = __umul24((unsigned)kl, (unsigned)(S * sizeof(R))) + ((unsigned)l * (unsigned)sizeof(R));
+        const R *t = reinterpret_cast<const R *>(reinterpret_cast<const char *>(tab) + ob);
+        R p00 = t[0], p01 = t[1], p10 = t[S], p11 = t[S + 1];
         // keep the LDS reads unconditional: without this the compiler folds
         // the two sources into one FLAT load
         asm("" : "+v"(p00), "+v"(p01), "+v"(p10), "+v"(p11));
