@@ -51,6 +51,9 @@ def parse():
     p.add_argument("--lds-rows", type=int, default=-1)
     p.add_argument("--j-chunks", type=int, default=0)
     p.add_argument("--grid-blocks", type=int, default=0)
+    p.add_argument("--no-graph", action="store_true",
+                   help="batch workload: call enl_potential_batched per step instead of replaying a recorded graph")
+    p.add_argument("--autotune", action="store_true", help="pick j_chunks with the autotuner before timing")
     p.add_argument("--copy-calib", type=int, default=0,
                    help="MiB: run one plain device-to-device copy of this size first (profiler calibration)")
     return p.parse_args()
@@ -85,7 +88,8 @@ def main():
                 "r<=30 bohr, n_cut=1e-5, table 2048x64, energy + potential fused")
     elif a.workload == "batch":
         wls = W.molecule_batch(64)
-        desc = "64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched call"
+        desc = ("64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched "
+                "evaluation (q0 included) replayed as a HIP graph")
     else:
         wls = [W.dimer_small()]
         desc = "dimer 24^3 grid h=0.5 bohr, n_cut=1e-6, table 1024x32, energy only"
@@ -106,7 +110,10 @@ def main():
         return V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec, kahan=a.kahan,
                       table_lds_rows=a.lds_rows, j_chunks=a.j_chunks, grid_blocks=a.grid_blocks)
 
-    def step(prec):
+    graph = a.workload == "batch" and not a.no_graph
+    plans = {}
+
+    def eager(prec):
         if a.workload == "batch":
             qd = V.compute_q0_batched(grids, n, offs, wl.n_cut)
             E, v = V.enl_potential_batched(grids, n, offs, qd, table, opts(prec))
@@ -117,25 +124,64 @@ def main():
         qd = V.compute_q0(g, n, wl.n_cut)
         return V.enl_potential(g, n, qd, table, opts(prec))
 
+    def step(prec):
+        if not graph:
+            return eager(prec)
+        p = plans.get(prec)
+        if p is None:
+            # the whole batched evaluation (q0 of every density included)
+            # recorded once into a HIP graph, replayed per step
+            p = plans[prec] = V.BatchPlan(grids, offs, table, opts(prec))
+            p.capture(n)
+        p.replay()
+        return p, None
+
+    def result(prec, out):
+        if not graph:
+            return out
+        p = out[0]
+        E = p.energies()
+        return tuple(sum(e[k] for e in E) for k in range(3)), p.dEdn
+
     def timed(prec, steps, warmup):
         V.set_timing(False)
         for i in range(warmup):
             step(prec)
+            torch.cuda.synchronize()
             print(f"# warmup {i + 1}/{warmup} precision={prec}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        V.set_timing(True)
+        V.set_timing(not graph)
         kms = []
         t0 = time.perf_counter()
         for i in range(steps):
-            E, v = step(prec)
-            kms.append(V.last_stats()["pair_kernel_ms"])
+            out = step(prec)
+            if not graph:
+                kms.append(V.last_stats()["pair_kernel_ms"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        E, v = result(prec, out)
+        if graph:
+            # pair-kernel time from HIP events around the same kernel in one
+            # eager evaluation (a replayed graph carries no events)
+            V.set_timing(True)
+            eager(prec)
+            kms.append(V.last_stats()["pair_kernel_ms"])
+        st = V.last_stats()
         V.set_timing(False)
         print(f"# timed {steps} steps precision={prec}: {dt:.3f} s", file=sys.stderr, flush=True)
-        return dt, E, v, float(np.mean(kms)), V.last_stats()
+        return dt, E, v, float(np.mean(kms)), st
 
     main_prec = V.VDW_FP64 if a.workload == "dimer24" else V.VDW_FP32C
+    if a.autotune:
+        from paper_0810_2273_amd import autotune
+
+        base = opts(main_prec)
+        tuned = autotune.tune(lambda o: V.enl_potential_batched(grids, n, offs, V.compute_q0_batched(
+            grids, n, offs, wl.n_cut), table, o), base, kept=int((n >= wl.n_cut).sum()),
+            nimg=int(np.prod([2 * m + 1 if per else 1 for m, per in zip(wl.image_max, wl.periodic)])),
+            batch=len(wls), verbose=True)
+        a.j_chunks = tuned.j_chunks
+        print(f"# autotune: j_chunks={a.j_chunks}", file=sys.stderr, flush=True)
     dt, E32, v32, kms32, st = timed(main_prec, a.steps, a.warmup)
     pairs = st["pairs"]
     value = pairs * a.steps / dt
@@ -160,6 +206,7 @@ def main():
             "j_chunks": st["j_chunks"],
             "grid_blocks": st["grid_blocks"],
             "kahan": a.kahan,
+            "hip_graph": graph,
         },
     }
     fpp = FLOP_PER_UNORDERED_PAIR_ENERGY if a.workload == "dimer24" else FLOP_PER_UNORDERED_PAIR

@@ -43,7 +43,7 @@ extern "C" {
 enum {
     VDW_OK = 0,
     VDW_EINVAL = -1,        /* bad argument: null pointer, size, parameter range  */
-    VDW_ENOMEM = -2,        /* device allocation failed (table builder scratch)   */
+    VDW_ENOMEM = -2,        /* host allocation failed (batch plan object)         */
     VDW_EHIP = -3,          /* a HIP runtime call failed                          */
     VDW_EUNSUPPORTED = -4,  /* valid but not implemented (skew cell with FD grad) */
     VDW_EWORKSPACE = -5,    /* workspace smaller than enl_workspace_size()        */
@@ -97,8 +97,9 @@ typedef struct {
                                compensated FP32 runs carried in FP64)             */
     int32_t self_term;      /* 1: add the on-site term E_self (below); 0: omit     */
     int32_t table_lds_rows; /* rows of the table kept in LDS; -1: as many as fit  */
-    int32_t block_threads;  /* pair-kernel workgroup size 256/512/1024; 0: auto   */
-    int32_t j_chunks;       /* split of the j range per i-block (1..64); 0: auto  */
+    int32_t block_threads;  /* pair-kernel workgroup size: 0 or 1024 (fixed)      */
+    int32_t j_chunks;       /* j-points per off-diagonal work item, in units of
+                               1024 (1..64); 0: auto (8)                          */
     int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
     int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only)     */
 } vdw_opts;
@@ -115,10 +116,11 @@ const char *vdw_version(void);
  *   phi_d: device, n_D * n_sigma doubles (written).
  *   phi_f: device, n_D * n_sigma floats, or NULL (FP32 copy for the
  *          VDW_FP32C pair kernel).
- * Allocates a small device scratch for the quadrature nodes (freed before
- * return) and synchronises `stream`.
+ * The Gauss-Legendre points of one panel are computed on the host and
+ * passed as kernel arguments, so nothing is allocated; synchronises
+ * `stream`.
  * Errors: VDW_EINVAL (null phi_d, n_D < 3, n_sigma < 2, D_max <= 0,
- * quadrature parameters out of range), VDW_ENOMEM, VDW_EHIP.
+ * quadrature parameters out of range), VDW_EHIP.
  * ------------------------------------------------------------------- */
 int build_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, void *stream);
 
@@ -207,6 +209,56 @@ int enl_potential_batched(int32_t B, const vdw_grid *grids, const int64_t *grid_
                           const double *dq_dg_d, const double *phi_d, const float *phi_f,
                           const vdw_table_params *tp, const vdw_opts *opts, void *ws, size_t ws_bytes,
                           double *dEdn_d, double *E_out, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batch plans -- the batched evaluation of enl_potential_batched split into
+ * a set-up step and a step that only launches kernels, so that a whole
+ * evaluation (gradient and q0 of every density, compaction, the persistent
+ * pair kernel over the shared work list, reductions, adjoint assembly; the
+ * same kernels and results as enl_potential_batched) can be recorded into
+ * a HIP graph and replayed, e.g. once per iteration of a self-consistent
+ * loop whose density buffer is rewritten in place.
+ *
+ * enl_batch_plan_create: validates the arguments, lays out the work for
+ *   these B grids (grid_off as for enl_potential_batched, always required;
+ *   potential = 1 for energy + dEdn, 0 for the energy only) and copies the
+ *   descriptors into the workspace `ws` (enl_batched_workspace_size bytes),
+ *   synchronising `stream`.  *plan receives a host object that keeps
+ *   pointing at `ws`: the workspace must outlive the plan and may not be
+ *   used by any other call meanwhile.
+ * enl_batch_plan_execute: enqueues one evaluation on `stream`: kernel
+ *   launches only (no copies, host waits or allocation).  It computes
+ *   grad_d (3 planes per density, as compute_q0), q0_d, dq_dn_d, dq_dg_d
+ *   (device, packed like n_d; the last three and dEdn_d may be NULL for an
+ *   energy-only plan) and writes
+ *     E_d: device, 4B+1 doubles: {E_pair0, E_pairL, E_self} for each
+ *          density, then the B retained-point counts, then a flag that is
+ *          non-zero when the density held NaN or Inf values.
+ *   Nothing is read back: the caller checks the flag.
+ * enl_batch_plan_capture: records one execute with these buffers into a
+ *   graph held by the plan (on a private stream; any earlier graph is
+ *   dropped).  The graph keeps the buffer addresses; new inputs go into
+ *   the same buffers.
+ * enl_batch_plan_replay: launches the recorded graph on `stream`.
+ *   Replays, executes and other calls on the same workspace are ordered
+ *   only by their streams; overlapping ones race.
+ * enl_batch_plan_destroy: frees the plan and its graph (NULL is a no-op).
+ * Errors: as enl_potential_batched; VDW_EINVAL for a NULL plan, a replay
+ * without a capture or missing buffers; VDW_EHIP for failed graph calls.
+ * ------------------------------------------------------------------- */
+typedef struct vdw_batch_plan vdw_batch_plan;
+
+int enl_batch_plan_create(int32_t B, const vdw_grid *grids, const int64_t *grid_off, const vdw_table_params *tp,
+                          const vdw_opts *opts, int32_t potential, void *ws, size_t ws_bytes,
+                          vdw_batch_plan **plan, void *stream);
+int enl_batch_plan_execute(vdw_batch_plan *plan, const double *n_d, double *grad_d, double *q0_d,
+                           double *dq_dn_d, double *dq_dg_d, const double *phi_d, const float *phi_f,
+                           double *dEdn_d, double *E_d, void *stream);
+int enl_batch_plan_capture(vdw_batch_plan *plan, const double *n_d, double *grad_d, double *q0_d,
+                           double *dq_dn_d, double *dq_dg_d, const double *phi_d, const float *phi_f,
+                           double *dEdn_d, double *E_d);
+int enl_batch_plan_replay(vdw_batch_plan *plan, void *stream);
+int enl_batch_plan_destroy(vdw_batch_plan *plan);
 
 /* ---------------------------------------------------------------------
  * Diagnostics of the last enl_* call on this host thread (after it

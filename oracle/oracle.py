@@ -475,13 +475,15 @@ def adjoint(grid: Grid, rho, qd, idx, nS, S0, Sq, Phi, dPhi):
     return v
 
 
-def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True):
+def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True,
+                        ops=None):
     """E(n + eps e_k) - E(n - eps e_k), recomputing only the rows whose n or
     q change (k and its finite-difference neighbours).  With P that set:
       sum over all pairs = (pairs outside P) + 2 R(P) - PP,
-      R(P) = sum_{i in P, j} n_i n_j phi~_ij,  PP = sum_{i, j in P}."""
+      R(P) = sum_{i in P, j} n_i n_j phi~_ij,  PP = sum_{i, j in P}.
+    `ops` may pass gradient_operators(grid) in, for repeated calls."""
     r0 = np.asarray(rho, dtype=np.float64).reshape(-1).copy()
-    ops = gradient_operators(grid)
+    ops = gradient_operators(grid) if ops is None else ops
     touched = set([int(k)])
     for Ga in ops:
         col = Ga.getcol(int(k)).tocoo()

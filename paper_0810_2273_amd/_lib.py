@@ -24,6 +24,8 @@ VDW_FP32C = 1
 EXPORTS = (
     "vdw_last_error", "vdw_version", "build_phi_table", "compute_q0", "enl_workspace_size", "enl_energy",
     "enl_potential", "enl_batched_workspace_size", "enl_potential_batched", "vdw_last_stats", "vdw_set_timing",
+    "enl_batch_plan_create", "enl_batch_plan_execute", "enl_batch_plan_capture", "enl_batch_plan_replay",
+    "enl_batch_plan_destroy",
 )
 
 
@@ -89,6 +91,17 @@ def lib():
     L.enl_potential_batched.restype = ct.c_int
     L.enl_potential_batched.argtypes = [i32, P(VdwGrid), P(ct.c_int64), vp, vp, vp, vp, vp, vp, vp,
                                         P(VdwTableParams), P(VdwOpts), vp, sz, vp, P(d), vp]
+    L.enl_batch_plan_create.restype = ct.c_int
+    L.enl_batch_plan_create.argtypes = [i32, P(VdwGrid), P(ct.c_int64), P(VdwTableParams), P(VdwOpts), i32, vp, sz,
+                                        P(vp), vp]
+    L.enl_batch_plan_execute.restype = ct.c_int
+    L.enl_batch_plan_execute.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.enl_batch_plan_capture.restype = ct.c_int
+    L.enl_batch_plan_capture.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.enl_batch_plan_replay.restype = ct.c_int
+    L.enl_batch_plan_replay.argtypes = [vp, vp]
+    L.enl_batch_plan_destroy.restype = ct.c_int
+    L.enl_batch_plan_destroy.argtypes = [vp]
     L.vdw_last_stats.restype = ct.c_int
     L.vdw_last_stats.argtypes = [P(VdwStats)]
     L.vdw_set_timing.restype = None

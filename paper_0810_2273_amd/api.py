@@ -242,6 +242,81 @@ def enl_potential_batched(grids, n_packed: torch.Tensor, offs, qd: dict, table: 
     return [(float(E[3 * b]), float(E[3 * b + 1]), float(E[3 * b + 2])) for b in range(B)], dEdn
 
 
+class BatchPlan:
+    """A batch plan (enl_batch_plan_*): the descriptors of B densities are
+    uploaded once; each ``execute`` then enqueues a whole evaluation (q0 of
+    every density, compaction, the persistent pair kernel, reductions, the
+    adjoint) as kernel launches only, which ``capture`` records into a HIP
+    graph that ``replay`` relaunches.  The plan owns its workspace and the
+    per-point buffers (grad, q0, dq_dn, dq_dg, dEdn) and ``E`` (4B+1 doubles:
+    3 energies per density, B retained counts, the non-finite flag)."""
+
+    def __init__(self, grids, offs, table: Table, opts: Opts, potential: bool = True, device="cuda", stream=None):
+        self._h = None
+        B = len(grids)
+        self.B, self.offs, self.table, self.potential = B, list(offs), table, bool(potential)
+        garr = (L.VdwGrid * B)(*[g.c() for g in grids])
+        off = (ct.c_int64 * (B + 1))(*offs)
+        tp, o = table.params.c(), opts.c()
+        nbytes = int(L.lib().enl_batched_workspace_size(B, garr, ct.byref(tp), ct.byref(o)))
+        if nbytes == 0:
+            raise L.VdwError(L.VDW_EINVAL, "invalid arguments for enl_batched_workspace_size")
+        Gt = offs[-1]
+        f64 = dict(dtype=torch.float64, device=device)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.q0 = torch.empty(Gt, **f64)
+        self.grad = torch.empty(3 * Gt, **f64) if potential else None
+        self.dq_dn = torch.empty(Gt, **f64) if potential else None
+        self.dq_dg = torch.empty(Gt, **f64) if potential else None
+        self.dEdn = torch.empty(Gt, **f64) if potential else None
+        self.E = torch.empty(4 * B + 1, **f64)
+        h = ct.c_void_p()
+        L.check(L.lib().enl_batch_plan_create(B, garr, off, ct.byref(tp), ct.byref(o), 1 if potential else 0,
+                                              _ptr(self.ws), self.ws.numel(), ct.byref(h), _stream(stream)))
+        self._h = h
+        self._bound = None
+
+    def _args(self, n):
+        _f64(n, "n")
+        if n.numel() != self.offs[-1]:
+            raise ValueError("n does not match the plan's grids")
+        return (_ptr(n), _ptr(self.grad), _ptr(self.q0), _ptr(self.dq_dn), _ptr(self.dq_dg), _ptr(self.table.phi64),
+                _ptr(self.table.phi32), _ptr(self.dEdn), _ptr(self.E))
+
+    def execute(self, n: torch.Tensor, stream=None):
+        L.check(L.lib().enl_batch_plan_execute(self._h, *self._args(n), _stream(stream)))
+
+    def capture(self, n: torch.Tensor):
+        """Record one evaluation on ``n`` (its buffer is read at every replay)."""
+        L.check(L.lib().enl_batch_plan_capture(self._h, *self._args(n)))
+        self._bound = n
+
+    def replay(self, stream=None):
+        L.check(L.lib().enl_batch_plan_replay(self._h, _stream(stream)))
+
+    def energies(self):
+        """[(E_pair0, E_pairL, E_self)] per density after the last evaluation
+        (waits for it); raises for a density that held NaN or Inf."""
+        e = self.E.cpu().tolist()
+        if e[4 * self.B] != 0.0:
+            raise L.VdwError(L.VDW_ENONFINITE, "the density holds NaN or Inf values")
+        return [(e[3 * b], e[3 * b + 1], e[3 * b + 2]) for b in range(self.B)]
+
+    def retained(self):
+        return [int(x) for x in self.E[3 * self.B:4 * self.B].cpu().tolist()]
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            L.check(L.lib().enl_batch_plan_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def last_stats() -> dict:
     s = L.VdwStats()
     L.check(L.lib().vdw_last_stats(ct.byref(s)))

@@ -33,9 +33,11 @@
 #include <math.h>
 #include <string.h>
 
+#include <new>
 #include <vector>
 
 #include "common.h"
+#include "q0_point.h"
 
 namespace vdw {
 
@@ -997,6 +999,23 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmArgs A)
 }
 
 // ---------------------------------------------------------------------------
+// gradient and q0 of every density of a packed batch (one launch)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restrict__ segs, int B, int64_t Gtot,
+                                                              double n_cut, const double *__restrict__ n,
+                                                              double *__restrict__ grad, double *__restrict__ q0,
+                                                              double *__restrict__ dqdn, double *__restrict__ dqdg)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Gtot) return;
+    const Seg &s = segs[find_seg(segs, B, t, 4)];
+    const int64_t o = s.grid_off;
+    grad_q0_point(n + o, (long)(t - o), s.nx, s.ny, s.nz, s.px, s.py, s.pz, s.hx, s.hy, s.hz, (long)s.G, n_cut,
+                  grad ? grad + 3 * o : nullptr, q0 + o, dqdn ? dqdn + o : nullptr, dqdg ? dqdg + o : nullptr);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -1144,9 +1163,6 @@ int validate_opts(const vdw_opts *o)
     return VDW_OK;
 }
 
-thread_local vdw_stats g_stats;
-thread_local int g_timing = 0;
-
 struct PairPtrs {
     const void *recs;
     const Seg *segs;
@@ -1160,13 +1176,16 @@ struct PairPtrs {
 };
 
 template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC>
-int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s)
+int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
     auto k = pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC>;
-    if (lds > 65536) {
-        // raises the dynamic-LDS limit where the runtime enforces one; a
-        // failure here surfaces at the launch below
-        (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (attr_only) {
+        // raises the dynamic-LDS limit where the runtime enforces one (done
+        // once per evaluation, outside any stream capture); a failure here
+        // surfaces at the launch
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        return VDW_OK;
     }
     hipLaunchKernelGGL(k, dim3(grid), dim3(kPairThreads), lds, s, a, (const typename RecOf<R>::T *)p.recs, p.segs,
                        p.hdr, p.counter, (const R *)p.tabg, p.imgs, p.rowoff, p.ipart, (R *)p.jpart);
@@ -1179,51 +1198,130 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 // compensated FP32C, and plain FP64; each with and without the adjoint
 // sums and the image loop.
 template <typename R, bool KAHAN, int NSIG, bool CUBIC>
-int launch_pair_v(int adj, int img, const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s)
+int launch_pair_v(int adj, int img, const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s,
+                  bool attr_only)
 {
-    if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s)
-                        : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s);
-    return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s)
-               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s);
+    if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only)
+                        : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only);
+    return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only)
+               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only);
 }
 
 int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, const PairArgs &a, const PairPtrs &p,
-                int grid, size_t lds, hipStream_t s)
+                int grid, size_t lds, hipStream_t s, bool attr_only)
 {
-    if (fp64) return launch_pair_v<double, false, 0, false>(adj, img, a, p, grid, lds, s);
-    if (kahan) return launch_pair_v<float, true, 0, false>(adj, img, a, p, grid, lds, s);
-    if (nsig == 64) return cubic ? launch_pair_v<float, false, 64, true>(adj, img, a, p, grid, lds, s)
-                                 : launch_pair_v<float, false, 64, false>(adj, img, a, p, grid, lds, s);
-    return launch_pair_v<float, false, 0, false>(adj, img, a, p, grid, lds, s);
+    if (fp64) return launch_pair_v<double, false, 0, false>(adj, img, a, p, grid, lds, s, attr_only);
+    if (kahan) return launch_pair_v<float, true, 0, false>(adj, img, a, p, grid, lds, s, attr_only);
+    if (nsig == 64) return cubic ? launch_pair_v<float, false, 64, true>(adj, img, a, p, grid, lds, s, attr_only)
+                                 : launch_pair_v<float, false, 64, false>(adj, img, a, p, grid, lds, s, attr_only);
+    return launch_pair_v<float, false, 0, false>(adj, img, a, p, grid, lds, s, attr_only);
 }
 
-// The whole pipeline for B densities.
-int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d, const double *q0_d,
-        const double *grad_d, const double *dqdn_d, const double *dqdg_d, const double *phi_d, const float *phi_f,
-        const vdw_table_params *tp, const vdw_opts *o, void *ws, size_t ws_bytes, double *dEdn_d, double *E_out,
-        hipStream_t s)
+// Everything an evaluation needs that does not depend on the data: the
+// work layout, the launch shapes and the constant kernel arguments.
+struct Exec {
+    Plan P;
+    int B = 0, adj = 0, fp64 = 0, kahan = 0, nsig = 0, cubic = 1, self_term = 0;
+    int K = 0, grid = 0;
+    size_t lds = 0;
+    double n_cut = 0.0, dD = 0.0, Dmax = 0.0, casym = 0.0;
+    int nD = 0;
+    PairArgs pa;
+    char *ws = nullptr;
+};
+
+constexpr double kCasym = 12.0 * (4.0 * 3.14159265358979323846 / 9.0) * (4.0 * 3.14159265358979323846 / 9.0) *
+                          (4.0 * 3.14159265358979323846 / 9.0);
+
+// Validation, layout and launch shapes (host only, no device work).
+int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_table_params *tp, const vdw_opts *o,
+            int adj, void *ws, size_t ws_bytes, Exec *E)
 {
     int rc = validate_opts(o);
     if (rc) return rc;
     rc = validate_table(tp);
     if (rc) return rc;
-    const int adj = dEdn_d != nullptr;
-    const int fp64 = o->precision == VDW_FP64;
     if (B < 1) return fail(VDW_EINVAL, "B must be >= 1");
-    if (!grids || !n_d || !q0_d || !phi_d || !E_out) return fail(VDW_EINVAL, "NULL argument");
-    if (!fp64 && !phi_f) return fail(VDW_EINVAL, "phi_f is required for VDW_FP32C");
-    if (adj && (!grad_d || !dqdn_d || !dqdg_d)) return fail(VDW_EINVAL, "grad_d, dq_dn_d and dq_dg_d are required");
+    if (!grids) return fail(VDW_EINVAL, "NULL argument");
     if (!ws) return fail(VDW_EINVAL, "workspace is NULL");
     DevInfo dev;
     rc = device_info(&dev);
     if (rc) return rc;
-    Plan P;
-    rc = make_plan(B, grids, grid_off, o, fp64, adj, &P);
+    E->B = B;
+    E->adj = adj;
+    E->fp64 = o->precision == VDW_FP64;
+    E->kahan = o->kahan;
+    E->nsig = tp->n_sigma;
+    E->self_term = o->self_term;
+    E->n_cut = o->n_cut;
+    rc = make_plan(B, grids, grid_off, o, E->fp64, adj, &E->P);
     if (rc) return rc;
-    if (ws_bytes < P.L.total)
-        return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
+    const Plan &P = E->P;
+    if (ws_bytes < P.L.total) return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
+    E->ws = (char *)ws;
+    const size_t esz = E->fp64 ? sizeof(double) : sizeof(float);
+    const int S = tp->n_sigma + 1;
+    const size_t red_bytes = (size_t)kWaves * P.NJ * 64 * esz;  // j-side tile sums
+    const size_t lds_cap = dev.lds_per_block > 256 + red_bytes ? dev.lds_per_block - 256 - red_bytes : 0;
+    int K = (int)(lds_cap / (S * esz));
+    if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
+    if (K > tp->n_D) K = tp->n_D;
+    if (K < 2) K = 2;  // the kernel reads a clamped LDS row unconditionally
+    E->K = K;
+    E->lds = (size_t)K * S * esz + red_bytes + 16;
+    E->grid = o->grid_blocks > 0 ? o->grid_blocks : dev.cus;
+    E->dD = tp->D_max / (tp->n_D - 1);
+    E->Dmax = tp->D_max;
+    E->nD = tp->n_D;
+    E->casym = kCasym;
+    PairArgs &pa = E->pa;
+    pa.B = B;
+    pa.nD = tp->n_D;
+    pa.nS = tp->n_sigma;
+    pa.S = S;
+    pa.K = K;
+    pa.JC = P.JC;
+    pa.csig = sqrt((double)(tp->n_sigma - 1));
+    pa.tDmax = (double)(tp->n_D - 1);
+    pa.tSclamp = E->fp64 ? nextafter((double)(tp->n_sigma - 1), 0.0)
+                         : (double)nextafterf((float)(tp->n_sigma - 1), 0.0f);
+    pa.casym = kCasym / pow(2.0 * E->dD, 6);  // the asymptote in units of h_x and a = q h_x / (2 dD)
+    pa.dD2 = 2.0 * E->dD;
+    pa.rc2 = o->r_cut > 0.0 ? o->r_cut * o->r_cut : INFINITY;
+    pa.nimg = P.nimg;
+    pa.home = P.home;
+    pa.NI = P.NI;
+    pa.NJ = P.NJ;
+    pa.istride = P.L.slots * kBI;
+    pa.jstride = P.L.slots * (int64_t)P.JC;
+    E->cubic = 1;
+    for (int b = 0; b < B; ++b)
+        if (!(P.segs[b].hx == P.segs[b].hy && P.segs[b].hx == P.segs[b].hz)) E->cubic = 0;
+    PairPtrs none{};
+    return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->cubic, pa, none, E->grid, E->lds, nullptr,
+                       true);
+}
+
+// Copies the density descriptors and the image list into the workspace.
+int upload(const Exec &E, hipStream_t s)
+{
+    const Layout &L = E.P.L;
+    VDW_HIP(hipMemcpyAsync(E.ws + L.segs, E.P.segs.data(), E.B * sizeof(Seg), hipMemcpyHostToDevice, s));
+    VDW_HIP(hipMemcpyAsync(E.ws + L.imgs, E.P.imgs.data(), E.P.imgs.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    return VDW_OK;
+}
+
+// The evaluation proper: kernel launches only (no copies, no host waits, no
+// allocation), so that it can be recorded into a HIP graph.  `res` receives
+// 4B+1 doubles: 3B energies, B retained counts, the non-finite flag.
+int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *grad_d, const double *dqdn_d,
+            const double *dqdg_d, const double *phi_d, const float *phi_f, double *dEdn_d, double *res, hipStream_t s,
+            hipEvent_t ev0, hipEvent_t ev1)
+{
+    const Plan &P = E.P;
     const Layout &L = P.L;
-    char *w = (char *)ws;
+    const int B = E.B;
+    char *w = E.ws;
     int64_t *hdr = (int64_t *)(w + L.hdr);
     int *counter = (int *)(w + L.counter);
     int *flag = (int *)(w + L.flag);
@@ -1236,17 +1334,14 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     double *ipart = (double *)(w + L.ipart);
     void *jpart = w + L.jpart;
     double *blockE = (double *)(w + L.blockE);
-    double *res = (double *)(w + L.res);
     double *dEdq = (double *)(w + L.dEdq);
 
-    VDW_HIP(hipMemcpyAsync(segs, P.segs.data(), B * sizeof(Seg), hipMemcpyHostToDevice, s));
-    VDW_HIP(hipMemcpyAsync(imgs, P.imgs.data(), P.imgs.size() * sizeof(int), hipMemcpyHostToDevice, s));
     // counter and flag live in 64-bit words right after the header
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, hdr, HDR_WORDS);
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, (int64_t *)counter, 1);
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, (int64_t *)flag, 1);
     VDW_HIP(hipGetLastError());
-    if (adj) {
+    if (E.adj) {
         unsigned gb = (unsigned)((L.Gtot + 255) / 256);
         hipLaunchKernelGGL(fill_kernel, dim3(gb), dim3(256), 0, s, dEdn_d, L.Gtot);
         hipLaunchKernelGGL(fill_kernel, dim3(gb), dim3(256), 0, s, dEdq, L.Gtot);
@@ -1254,7 +1349,7 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     }
     // compaction
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)L.nblocks), dim3(kCompactThreads), 0, s, (const Seg *)segs, B,
-                       n_d, o->n_cut, counts, flag);
+                       n_d, E.n_cut, counts, flag);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, L.nblocks, segs, B, hdr, rowoff,
                        (int64_t)P.JC);
     ScatterArgs sa;
@@ -1262,70 +1357,31 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     sa.B = B;
     sa.n = n_d;
     sa.q0 = q0_d;
-    sa.n_cut = o->n_cut;
+    sa.n_cut = E.n_cut;
     sa.offs = counts;
     sa.recs = recs;
     sa.gidx = gidx;
-    const double dD = tp->D_max / (tp->n_D - 1);
-    sa.inv2dD = 1.0 / (2.0 * dD);
-    sa.csig = sqrt((double)(tp->n_sigma - 1));
-    sa.fp64 = fp64;
+    sa.inv2dD = 1.0 / (2.0 * E.dD);
+    sa.csig = E.pa.csig;
+    sa.fp64 = E.fp64;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)L.nblocks), dim3(kCompactThreads), 0, s, sa);
     VDW_HIP(hipGetLastError());
 
     // pair kernel
-    const size_t esz = fp64 ? sizeof(double) : sizeof(float);
-    const int S = tp->n_sigma + 1;
-    const size_t red_bytes = (size_t)kWaves * P.NJ * 64 * esz;  // j-side tile sums
-    const size_t lds_cap = dev.lds_per_block > 256 + red_bytes ? dev.lds_per_block - 256 - red_bytes : 0;
-    int K = (int)(lds_cap / (S * esz));
-    if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
-    if (K > tp->n_D) K = tp->n_D;
-    if (K < 2) K = 2;  // the kernel reads a clamped LDS row unconditionally
-    PairArgs pa;
-    pa.B = B;
-    pa.nD = tp->n_D;
-    pa.nS = tp->n_sigma;
-    pa.S = S;
-    pa.K = K;
-    pa.JC = P.JC;
-    pa.csig = sqrt((double)(tp->n_sigma - 1));
-    pa.tDmax = (double)(tp->n_D - 1);
-    pa.tSclamp = fp64 ? nextafter((double)(tp->n_sigma - 1), 0.0) : (double)nextafterf((float)(tp->n_sigma - 1), 0.0f);
-    const double Casym = 12.0 * pow(4.0 * 3.14159265358979323846 / 9.0, 3);
-    pa.casym = Casym / pow(2.0 * dD, 6);  // the asymptote in units of h_x and a = q h_x / (2 dD)
-    pa.dD2 = 2.0 * dD;
-    pa.rc2 = o->r_cut > 0.0 ? o->r_cut * o->r_cut : INFINITY;
-    pa.nimg = P.nimg;
-    pa.home = P.home;
-    pa.NI = P.NI;
-    pa.NJ = P.NJ;
-    pa.istride = L.slots * kBI;
-    pa.jstride = L.slots * (int64_t)P.JC;
     PairPtrs pp;
     pp.recs = recs;
     pp.segs = segs;
     pp.hdr = hdr;
     pp.counter = counter;
-    pp.tabg = fp64 ? (const void *)phi_d : (const void *)phi_f;
+    pp.tabg = E.fp64 ? (const void *)phi_d : (const void *)phi_f;
     pp.imgs = imgs;
     pp.rowoff = rowoff;
     pp.ipart = ipart;
     pp.jpart = jpart;
-    int grid = o->grid_blocks > 0 ? o->grid_blocks : dev.cus;
-    size_t lds = (size_t)K * S * esz + red_bytes + 16;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (g_timing) {
-        VDW_HIP(hipEventCreate(&ev0));
-        VDW_HIP(hipEventCreate(&ev1));
-        VDW_HIP(hipEventRecord(ev0, s));
-    }
-    int cubic = 1;
-    for (int b = 0; b < B; ++b)
-        if (!(P.segs[b].hx == P.segs[b].hy && P.segs[b].hx == P.segs[b].hz)) cubic = 0;
-    rc = launch_pair(fp64, adj, P.img ? 1 : 0, o->kahan, tp->n_sigma, cubic, pa, pp, grid, lds, s);
+    if (ev0) VDW_HIP(hipEventRecord(ev0, s));
+    int rc = launch_pair(E.fp64, E.adj, P.img ? 1 : 0, E.kahan, E.nsig, E.cubic, E.pa, pp, E.grid, E.lds, s, false);
     if (rc) return rc;
-    if (g_timing) VDW_HIP(hipEventRecord(ev1, s));
+    if (ev1) VDW_HIP(hipEventRecord(ev1, s));
 
     // finalize and reduce
     FinArgs fa;
@@ -1335,25 +1391,25 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     fa.rowoff = rowoff;
     fa.ipart = ipart;
     fa.jpart = jpart;
-    fa.jfp64 = fp64;
-    fa.istride = pa.istride;
-    fa.jstride = pa.jstride;
+    fa.jfp64 = E.fp64;
+    fa.istride = E.pa.istride;
+    fa.jstride = E.pa.jstride;
     fa.JC = P.JC;
     fa.NI = P.NI;
     fa.NJ = P.NJ;
     fa.img = P.img ? 1 : 0;
-    fa.adj = adj;
-    fa.self_term = o->self_term;
+    fa.adj = E.adj;
+    fa.self_term = E.self_term;
     fa.gidx = gidx;
     fa.n = n_d;
     fa.q0 = q0_d;
     fa.dqdn = dqdn_d;
     fa.tab = phi_d;
-    fa.nD = tp->n_D;
-    fa.nS = tp->n_sigma;
-    fa.dD = dD;
-    fa.Dmax = tp->D_max;
-    fa.casym = Casym;
+    fa.nD = E.nD;
+    fa.nS = E.nsig;
+    fa.dD = E.dD;
+    fa.Dmax = E.Dmax;
+    fa.casym = E.casym;
     fa.blockE = blockE;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
@@ -1362,7 +1418,7 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     hipLaunchKernelGGL(seg_reduce_kernel, dim3(B), dim3(256), 0, s, (const Seg *)segs, (const double *)blockE, res, B,
                        (const int *)flag);
     VDW_HIP(hipGetLastError());
-    if (adj) {
+    if (E.adj) {
         AsmArgs aa;
         aa.segs = segs;
         aa.B = B;
@@ -1374,33 +1430,68 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
         hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((L.Gtot + 255) / 256)), dim3(256), 0, s, aa);
         VDW_HIP(hipGetLastError());
     }
-    std::vector<double> host(4 * B + 1);
-    VDW_HIP(hipMemcpyAsync(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    VDW_HIP(hipStreamSynchronize(s));
-    float ms = 0.0f;
-    if (g_timing) {
-        VDW_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
-    }
-    if (host[4 * B] != 0.0) return fail(VDW_ENONFINITE, "the density holds NaN or Inf values");
+    return VDW_OK;
+}
+
+thread_local vdw_stats g_stats;
+thread_local int g_timing = 0;
+
+void set_stats(const Exec &E, const double *host, float ms)
+{
     double pairs = 0.0;
     int64_t retained = 0;
-    for (int b = 0; b < B; ++b) {
-        E_out[3 * b + 0] = host[3 * b + 0];
-        E_out[3 * b + 1] = host[3 * b + 1];
-        E_out[3 * b + 2] = host[3 * b + 2];
-        double Nb = host[3 * B + b];
+    for (int b = 0; b < E.B; ++b) {
+        double Nb = host[3 * E.B + b];
         retained += (int64_t)Nb;
-        pairs += Nb * Nb * P.nimg - Nb;
+        pairs += Nb * Nb * E.P.nimg - Nb;
     }
     g_stats.retained = retained;
     g_stats.pairs = pairs;
     g_stats.pair_kernel_ms = ms;
-    g_stats.lds_rows = K;
+    g_stats.lds_rows = E.K;
     g_stats.block_threads = kPairThreads;
-    g_stats.j_chunks = P.JC / 1024;
-    g_stats.grid_blocks = grid;
+    g_stats.j_chunks = E.P.JC / 1024;
+    g_stats.grid_blocks = E.grid;
+}
+
+// The whole pipeline for B densities, energies read back to the host.
+int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d, const double *q0_d,
+        const double *grad_d, const double *dqdn_d, const double *dqdg_d, const double *phi_d, const float *phi_f,
+        const vdw_table_params *tp, const vdw_opts *o, void *ws, size_t ws_bytes, double *dEdn_d, double *E_out,
+        hipStream_t s)
+{
+    const int adj = dEdn_d != nullptr;
+    if (!n_d || !q0_d || !phi_d || !E_out) return fail(VDW_EINVAL, "NULL argument");
+    if (o && o->precision == VDW_FP32C && !phi_f) return fail(VDW_EINVAL, "phi_f is required for VDW_FP32C");
+    if (adj && (!grad_d || !dqdn_d || !dqdg_d)) return fail(VDW_EINVAL, "grad_d, dq_dn_d and dq_dg_d are required");
+    Exec E;
+    int rc = prepare(B, grids, grid_off, tp, o, adj, ws, ws_bytes, &E);
+    if (rc) return rc;
+    rc = upload(E, s);
+    if (rc) return rc;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (g_timing) {
+        VDW_HIP(hipEventCreate(&ev0));
+        VDW_HIP(hipEventCreate(&ev1));
+    }
+    double *res = (double *)(E.ws + E.P.L.res);
+    rc = enqueue(E, n_d, q0_d, grad_d, dqdn_d, dqdg_d, phi_d, phi_f, dEdn_d, res, s, ev0, ev1);
+    std::vector<double> host(4 * B + 1);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = fail(VDW_EHIP, "reading the energies back: %s", hipGetErrorString(e));
+    }
+    float ms = 0.0f;
+    if (ev0) {
+        if (!rc && hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) ms = 0.0f;
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    if (rc) return rc;
+    if (host[4 * B] != 0.0) return fail(VDW_ENONFINITE, "the density holds NaN or Inf values");
+    for (int k = 0; k < 3 * B; ++k) E_out[k] = host[k];
+    set_stats(E, host.data(), ms);
     return VDW_OK;
 }
 
@@ -1463,3 +1554,117 @@ extern "C" int vdw_last_stats(vdw_stats *out)
 }
 
 extern "C" void vdw_set_timing(int32_t on) { g_timing = on ? 1 : 0; }
+
+// ---------------------------------------------------------------------------
+// batch plans: descriptors uploaded once, then kernel-only evaluations that a
+// HIP graph can record and replay
+// ---------------------------------------------------------------------------
+
+struct vdw_batch_plan {
+    vdw::Exec E;
+    std::vector<int64_t> grid_off;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int enl_batch_plan_create(int32_t B, const vdw_grid *grids, const int64_t *grid_off,
+                                     const vdw_table_params *tp, const vdw_opts *opts, int32_t potential, void *ws,
+                                     size_t ws_bytes, vdw_batch_plan **plan, void *stream)
+{
+    if (!plan) return fail(VDW_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (!grid_off) return fail(VDW_EINVAL, "grid_off is NULL");
+    if (B >= 1 && grid_off[0] != 0) return fail(VDW_EINVAL, "grid_off[0] must be 0");
+    if (potential != 0 && potential != 1) return fail(VDW_EINVAL, "potential must be 0 or 1");
+    vdw_batch_plan *p = new (std::nothrow) vdw_batch_plan;
+    if (!p) return fail(VDW_ENOMEM, "out of host memory");
+    int rc = prepare(B, grids, grid_off, tp, opts, potential, ws, ws_bytes, &p->E);
+    if (!rc) rc = upload(p->E, (hipStream_t)stream);
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) rc = fail(VDW_EHIP, "uploading the plan: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    p->grid_off.assign(grid_off, grid_off + B + 1);
+    *plan = p;
+    return VDW_OK;
+}
+
+extern "C" int enl_batch_plan_execute(vdw_batch_plan *plan, const double *n_d, double *grad_d, double *q0_d,
+                                      double *dq_dn_d, double *dq_dg_d, const double *phi_d, const float *phi_f,
+                                      double *dEdn_d, double *E_d, void *stream)
+{
+    if (!plan) return fail(VDW_EINVAL, "plan is NULL");
+    const Exec &E = plan->E;
+    if (!n_d || !q0_d || !phi_d || !E_d) return fail(VDW_EINVAL, "NULL argument");
+    if (!E.fp64 && !phi_f) return fail(VDW_EINVAL, "phi_f is required for VDW_FP32C");
+    if (E.adj && (!grad_d || !dq_dn_d || !dq_dg_d || !dEdn_d))
+        return fail(VDW_EINVAL, "a potential plan needs grad_d, dq_dn_d, dq_dg_d and dEdn_d");
+    hipStream_t s = (hipStream_t)stream;
+    const Layout &L = E.P.L;
+    hipLaunchKernelGGL(grad_q0_batched_kernel, dim3((unsigned)((L.Gtot + 255) / 256)), dim3(256), 0, s,
+                       (const Seg *)(E.ws + L.segs), E.B, L.Gtot, E.n_cut, n_d, grad_d, q0_d, dq_dn_d, dq_dg_d);
+    VDW_HIP(hipGetLastError());
+    return enqueue(E, n_d, q0_d, grad_d, dq_dn_d, dq_dg_d, phi_d, phi_f, E.adj ? dEdn_d : nullptr, E_d, s, nullptr,
+                   nullptr);
+}
+
+extern "C" int enl_batch_plan_capture(vdw_batch_plan *plan, const double *n_d, double *grad_d, double *q0_d,
+                                      double *dq_dn_d, double *dq_dg_d, const double *phi_d, const float *phi_f,
+                                      double *dEdn_d, double *E_d)
+{
+    if (!plan) return fail(VDW_EINVAL, "plan is NULL");
+    if (plan->exec) {
+        (void)hipGraphExecDestroy(plan->exec);
+        plan->exec = nullptr;
+    }
+    if (plan->graph) {
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    hipStream_t cs = nullptr;
+    VDW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return fail(VDW_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    int rc = enl_batch_plan_execute(plan, n_d, grad_d, q0_d, dq_dn_d, dq_dg_d, phi_d, phi_f, dEdn_d, E_d, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(VDW_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        plan->exec = nullptr;
+        return fail(VDW_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    plan->graph = g;
+    return VDW_OK;
+}
+
+extern "C" int enl_batch_plan_replay(vdw_batch_plan *plan, void *stream)
+{
+    if (!plan) return fail(VDW_EINVAL, "plan is NULL");
+    if (!plan->exec) return fail(VDW_EINVAL, "the plan holds no captured graph");
+    VDW_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return VDW_OK;
+}
+
+extern "C" int enl_batch_plan_destroy(vdw_batch_plan *plan)
+{
+    if (!plan) return VDW_OK;
+    int rc = VDW_OK;
+    if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) rc = fail(VDW_EHIP, "hipGraphExecDestroy failed");
+    if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) rc = fail(VDW_EHIP, "hipGraphDestroy failed");
+    delete plan;
+    return rc;
+}

@@ -87,3 +87,36 @@ def test_host_side_validation(L):
     assert lib.enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)) > 0
     o.j_chunks = 99
     assert lib.enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)) == 0
+
+
+def test_batch_plan_host_validation(L):
+    """The plan entry points reject NULL handles and arguments on the host."""
+    lib = L.lib()
+    dummy = ct.c_void_p(16)
+    h = ct.c_void_p()
+    g = L.VdwGrid()
+    for a in range(3):
+        g.n[a] = 8
+        g.cell[a][a] = 4.0
+    tp = L.VdwTableParams(64, 16, 12.0, 8, 12, 4.0, 64.0)
+    o = L.VdwOpts()
+    o.n_cut = 1e-5
+    o.precision = 1
+    offs = (ct.c_int64 * 2)(0, 512)
+    assert lib.enl_batch_plan_create(1, ct.byref(g), offs, ct.byref(tp), ct.byref(o), 1, dummy, 1 << 20, None,
+                                     None) == L.VDW_EINVAL
+    assert lib.enl_batch_plan_create(1, ct.byref(g), None, ct.byref(tp), ct.byref(o), 1, dummy, 1 << 20,
+                                     ct.byref(h), None) == L.VDW_EINVAL
+    assert h.value is None
+    assert lib.enl_batch_plan_create(1, ct.byref(g), offs, ct.byref(tp), ct.byref(o), 2, dummy, 1 << 20,
+                                     ct.byref(h), None) == L.VDW_EINVAL
+    o.precision = 7
+    assert lib.enl_batch_plan_create(1, ct.byref(g), offs, ct.byref(tp), ct.byref(o), 1, dummy, 1 << 20,
+                                     ct.byref(h), None) == L.VDW_EINVAL
+    assert h.value is None
+    assert lib.enl_batch_plan_execute(None, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy,
+                                      None) == L.VDW_EINVAL
+    assert lib.enl_batch_plan_capture(None, dummy, dummy, dummy, dummy, dummy, dummy, dummy, dummy,
+                                      dummy) == L.VDW_EINVAL
+    assert lib.enl_batch_plan_replay(None, None) == L.VDW_EINVAL
+    assert lib.enl_batch_plan_destroy(None) == L.VDW_OK

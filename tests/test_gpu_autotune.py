@@ -1,0 +1,49 @@
+"""The j-chunk autotuner: it times each candidate with the pair kernel's HIP
+events, keeps the fastest, caches the choice, and the tuned evaluation gives
+the same result (the chunk length changes the summation order only)."""
+import json
+
+import pytest
+
+import vdw_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_picks_and_caches(tmp_path, monkeypatch):
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0810_2273_amd as V
+    from paper_0810_2273_amd import autotune
+
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("VDW_AUTOTUNE_CACHE", str(cache))
+    wl = W.scaled_dimer(edge=48, h=0.3)
+    g = V.Grid(wl.n, wl.h)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    table = V.build_phi_table(V.TableParams(n_D=512, n_sigma=32, D_max=48.0, gl_points=6, graded_levels=8,
+                                            kappa=2.0, A0=20.0))
+    qd = V.compute_q0(g, n, wl.n_cut)
+    kept = int((n >= wl.n_cut).sum())
+    print(f"autotune on a 48^3 dimer ({kept} kept points)", flush=True)
+
+    def run(o):
+        return V.enl_potential(g, n, qd, table, o)
+
+    base = V.Opts(n_cut=wl.n_cut, precision=0)
+    tuned = autotune.tune(run, base, kept=kept, candidates=(1, 2, 4, 8), repeats=1, verbose=True)
+    assert tuned.j_chunks in (1, 2, 4, 8)
+    data = json.loads(cache.read_text())
+    (entry,) = data.values()
+    assert entry["j_chunks"] == tuned.j_chunks and set(entry["sweep"]) == {"1", "2", "4", "8"}
+    assert min(entry["sweep"].values()) == entry["ms"] > 0
+    # the cached choice comes back without timing
+    again = autotune.tune(lambda o: pytest.fail("re-timed a cached workload"), base, kept=kept)
+    assert again.j_chunks == tuned.j_chunks
+    E0, v0 = run(base)
+    E1, v1 = run(tuned)
+    assert sum(E1) == pytest.approx(sum(E0), rel=1e-12)
+    assert float(torch.linalg.norm(v1 - v0) / torch.linalg.norm(v0)) <= 1e-12
+    assert V.last_stats()["j_chunks"] == tuned.j_chunks

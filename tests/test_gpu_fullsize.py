@@ -93,6 +93,89 @@ def test_kr_dimer_full_size_sampled_potential(V, oracle, big, prec, vtol):
     _sampled_check(V, oracle, wl, tp, tab, ks, prec, vtol)
 
 
+def _kr_potential(V, wl, table, prec):
+    import torch
+
+    g = V.Grid(wl.n, wl.h, wl.periodic)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    E, v = V.enl_potential(g, n, qd, table, V.Opts(n_cut=wl.n_cut, precision=prec))
+    return E, v.cpu().numpy()
+
+
+def test_kr_dimer_adjoint_vs_finite_differences(V, oracle, big):
+    """dE/dn of the GPU (FP64, fused energy + adjoint) on the R = 7 bohr
+    96^3 dimer at 64 random kept points and 8 dropped points next to kept
+    ones, against central finite differences of the oracle energy with step
+    1e-4 n_k (only the rows whose n or q the step changes are recomputed).
+
+    FD of the bilinear table interpolant is not its derivative: a step moves
+    a few per cent of the pairs' D across a table kink (and some across the
+    switch at D_max), which puts an O(eps) gap of 1e-5..1e-3 between FD and
+    the exact derivative, largest where the terms of dE/dn cancel.  So the
+    GPU must equal the oracle's exact adjoint at these points (1e-10), be no
+    further from FD than that adjoint is, and agree with FD to 4e-4 in the
+    norm over all points; a dropped chain-rule term moves v by 10-50 %."""
+    tp, tab = big
+    wl = W.kr_dimer(7.0)
+    say("kr dimer: adjoint vs central finite differences (64 + 8 points)")
+    _, v = _kr_potential(V, wl, _gpu_table(V, tp, tab), 0)
+    rho = wl.rho.reshape(-1)
+    g = oracle.Grid(wl.n, wl.h, wl.periodic)
+    ops = oracle.gradient_operators(g)
+    rng = np.random.default_rng(64)
+    ks = list(rng.choice(np.flatnonzero(rho >= wl.n_cut), 64, replace=False))
+    Gx = ops[0].tocsc()
+    dropped = np.flatnonzero(rho < 0.99 * wl.n_cut)
+    ks += [int(k) for k in rng.permutation(dropped)[:20000]
+           if np.any(rho[Gx.getcol(int(k)).indices] >= wl.n_cut)][:8]
+    ks = np.array(ks)
+    fd = np.empty(len(ks))
+    for t, k in enumerate(ks):
+        eps = 1e-4 * rho[k]
+        fd[t] = oracle.local_energy_change(g, wl.rho, k, eps, tab, tp, wl.n_cut, ops=ops) / (2 * eps)
+    ref = oracle.potential_at(g, wl.rho, ks, tab, tp, wl.n_cut)
+    gv = v[ks]
+    say(f"  GPU vs exact adjoint: {np.linalg.norm(gv - ref) / np.linalg.norm(ref):.3e}; GPU vs FD: max per point "
+        f"{np.max(np.abs(gv - fd) / np.abs(fd)):.3e}, L2 {np.linalg.norm(gv - fd) / np.linalg.norm(fd):.3e}")
+    assert np.linalg.norm(gv - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.all(np.abs(gv - fd) <= np.abs(ref - fd) + 1e-9 * np.abs(ref))
+    assert np.linalg.norm(gv - fd) <= 4e-4 * np.linalg.norm(fd)
+    assert np.all(np.abs(gv - fd) <= 1e-2 * np.abs(fd))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,vtol", [(0, 1e-10), (1, 1e-4)])
+def test_kr_dimer_potential_on_24_cubed_subgrid(V, oracle, big, prec, vtol):
+    """The GPU potential on the R = 7 bohr dimer against the oracle gradient on
+    the 24^3 subgrid of every 4th grid node (13 824 points, most of them
+    kept), FP64 and FP32C."""
+    tp, tab = big
+    wl = W.kr_dimer(7.0)
+    say(f"kr dimer: potential on the 24^3 subgrid, precision={prec}")
+    _, v = _kr_potential(V, wl, _gpu_table(V, tp, tab), prec)
+    sub = np.zeros(wl.rho.shape, dtype=bool)
+    sub[::4, ::4, ::4] = True
+    ks = np.flatnonzero(sub.reshape(-1))
+    ref = _subgrid_ref(oracle, wl, tp, tab, ks)
+    rel = np.linalg.norm(v[ks] - ref) / np.linalg.norm(ref)
+    say(f"  |dv|/|v| over {len(ks)} points = {rel:.3e}")
+    assert rel <= vtol
+    # dropped points outside every kept stencil get exactly nothing
+    zero = ref == 0.0
+    assert np.all(v[ks][zero] == 0.0)
+
+
+_SUBGRID = {}
+
+
+def _subgrid_ref(oracle, wl, tp, tab, ks):
+    key = (wl.name, len(ks))
+    if key not in _SUBGRID:
+        _SUBGRID[key] = oracle.potential_at(oracle.Grid(wl.n, wl.h, wl.periodic), wl.rho, ks, tab, tp, wl.n_cut)
+    return _SUBGRID[key]
+
+
 def test_kr_dimer_full_size_energy_properties(V, big):
     """Full-size energies: FP32C within 1e-6 of FP64 (and v within 1e-4), the
     energy-only kernel equal to the fused one, and the R-scan binding curve
