@@ -30,10 +30,10 @@ if ROOT not in sys.path:
 FLOP_PER_UNORDERED_PAIR = 45
 FLOP_PER_UNORDERED_PAIR_ENERGY = 30
 PEAK_FP32_TFLOPS = 157.3
-# HBM bytes per pair-kernel launch on the Kr2-like dimer, from rocprofv3
-# FETCH_SIZE (x 2.0, the factor a plain 512 MiB copy needs) + WRITE_SIZE of the
-# current kernel (profiles/pair_kernel_kr_dimer96_fp32c.md); None elsewhere.
-TRAFFIC_BYTES = {"kr": (1039380.375 * 2.0 + 961572.15625) * 1024}
+# HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
+# factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
+# (profiles/); a workload without a profile of the current kernel has none.
+TRAFFIC_BYTES = {}
 
 
 def parse():

@@ -50,6 +50,15 @@ constexpr int kWaves = kPairThreads / 64;
 constexpr int kBI = 2 * kPairThreads; // i-points per row block (two per lane)
 constexpr int kFinThreads = 256;      // points per finalize block
 constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 carry (diagonal items)
+constexpr int kLdsBytes = 160 * 1024; // LDS of one gfx950 workgroup
+
+// Table elements a pair workgroup keeps in LDS, next to its j-side
+// reduction buffer (kWaves x NJ x 64) and the work-item slot.
+template <typename R>
+constexpr int tab_elems(int NJ)
+{
+    return (int)((kLdsBytes - kWaves * NJ * 64 * sizeof(R) - 64) / sizeof(R));
+}
 
 enum { HDR_ITEMS = 0, HDR_NTOTAL = 1, HDR_BLKS = 2, HDR_WORDS = 8 };
 
@@ -66,11 +75,13 @@ struct Seg {
     int64_t N, p_off, item_off, blk_off, nIB, items;
 };
 
+// Kept point: grid coordinates (exact integers), n, a = q h_x / (2 dD),
+// b = sqrt(n_sigma - 1) a, w = x^2 + y^2 + z^2 (exact).
 struct alignas(32) RecF {
-    float x, y, z, n, a, b, p, pad;
+    float x, y, z, n, a, b, w, pad;
 };
 struct alignas(64) RecD {
-    double x, y, z, n, a, b, p, pad;
+    double x, y, z, n, a, b, w, pad;
 };
 
 // ---------------------------------------------------------------------------
@@ -273,7 +284,7 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
             r.n = nn;
             r.a = a;
             r.b = a * A.csig;
-            r.p = q * q;
+            r.w = (double)xs[u] * xs[u] + (double)ys[u] * ys[u] + (double)zs[u] * zs[u];
             r.pad = 0.0;
             ((RecD *)A.recs)[pos] = r;
         } else {
@@ -284,7 +295,7 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
             r.n = (float)nn;
             r.a = (float)a;
             r.b = (float)(a * A.csig);
-            r.p = (float)(q * q);
+            r.w = (float)((double)xs[u] * xs[u] + (double)ys[u] * ys[u] + (double)zs[u] * zs[u]);
             r.pad = 0.0f;
             ((RecF *)A.recs)[pos] = r;
         }
@@ -347,7 +358,7 @@ __device__ inline double wrot(double x)
 
 template <typename R>
 struct PairK {
-    R tDmax, tSclamp, csig, c4, casym, wy, wz;
+    R tDmax, tDlds, tSclamp, csig, c4, casym, wy, wz;
     int S, nS, K;
 };
 
@@ -368,73 +379,142 @@ __device__ __forceinline__ R dist2(const PairK<R> &k, R dx, R dy, R dz)
     return dx * dx + (k.wy * dy) * dy + (k.wz * dz) * dz;
 }
 
+// Squared distance on a cubic grid as |x_i|^2 + |x_j|^2 - 2 x_i . x_j with
+// (mx, my, mz) = -2 x_i and w = |x_i|^2 + |x_j|^2: every term and partial
+// sum is an integer below 2^24 (the host checks the coordinate range), so
+// the FP32 result is exact and equals the difference form.
+__device__ __forceinline__ float dist2n(float mx, float my, float mz, float w, float xj, float yj, float zj)
+{
+    return fmaf(mx, xj, fmaf(my, yj, fmaf(mz, zj, w)));
+}
+
+// The table interpolant at fractions (fD, fS) of the cell whose corners are
+// p00 = phi(k, l), p01 = phi(k, l+1), p10 = phi(k+1, l), p11 = phi(k+1, l+1),
+// and (ADJ) the q-derivatives: gD r + gS u inv^2 4 csig a_j for q_i, and the
+// sigma term with the sign flipped and a_j -> a_i for q_j.
+template <typename R, bool ADJ, bool JSIDE>
+__device__ __forceinline__ void bilinear(R p00, R p01, R p10, R p11, R fD, R fS, R r, R u, R inv, R c4, R ai, R aj,
+                                         R &phi, R &dqi, R &dqj)
+{
+    const R d0 = p01 - p00, d1 = p11 - p10;
+    const R lo = p00 + fS * d0, hi = p10 + fS * d1;
+    const R gD = hi - lo;
+    phi = lo + fD * gD;
+    if (ADJ) {
+        const R gS = d0 + fD * (d1 - d0);
+        const R X = gD * r;
+        const R Y = (gS * (u * inv)) * (inv * c4);
+        dqi = X + Y * aj;
+        if (JSIDE) dqj = X - Y * ai;
+    }
+}
+
+// The large-D asymptote -C' / (m^3 a_i^2 a_j^2 (a_i^2 + a_j^2)) and its
+// q-derivatives.
+template <typename R, bool ADJ, bool JSIDE>
+__device__ __forceinline__ void asymptote(const PairK<R> &k, R m, R ai, R aj, R &phi, R &dqi, R &dqj)
+{
+    // a private copy keeps these rare-branch products from being hoisted
+    R ajx = aj;
+    asm("" : "+v"(ajx));
+    const R pi = ai * ai, pj = ajx * ajx, pp = pi + pj;
+    phi = -k.casym * drcp(m * m * m * pi * pj * pp);
+    if (ADJ) {
+        const R rp = drcp(pp);
+        dqi = -phi * ((R)2 * drcp(ai) + (R)2 * ai * rp);
+        if (JSIDE) dqj = -phi * ((R)2 * drcp(ajx) + (R)2 * ajx * rp);
+    }
+}
+
 // phi~ of one pair and (ADJ) the q-derivatives, from m = r^2 / h_x^2 and
-// a = q h_x / (2 dD) of both points (b_i = csig a_i):
+// a = q h_x / (2 dD) of both points:
 //   t_D = (a_i + a_j) sqrt(m) = D / dD,  u = csig (a_i - a_j)/(a_i + a_j),  t_s = u^2 = sigma (n_sigma - 1)
 //   table branch: bilinear in (t_D, t_s);  beyond: -C' / (m^3 a_i^2 a_j^2 (a_i^2 + a_j^2)),  C' = C / (2 dD)^6
 // dqi, dqj are 2 dD / h_x times d phi~ / d q_i and d phi~ / d q_j.
-template <typename R, bool ADJ, bool JSIDE, int NSIG>
-__device__ __forceinline__ void pair_eval(const PairK<R> &k, const R *tab, const R *__restrict__ tabg, R m, R ai,
-                                          R bi, R aj, R caj, R &phi, R &dqi, R &dqj)
+// FP64 form: ci = b_i = csig a_i and cj = csig a_j, u = (b_i - csig a_j) / s.
+template <bool ADJ, bool JSIDE, int NSIG>
+__device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *tab, const double *__restrict__ tabg,
+                                          double m, double ai, double ci, double aj, double cj, double &phi,
+                                          double &dqi, double &dqj)
 {
     const int S = NSIG ? NSIG + 1 : k.S;
     const int nS = NSIG ? NSIG : k.nS;
-    const R r = dsqrt(m);
-    const R s = ai + aj;
-    const R tD = s * r;
+    const double r = dsqrt(m);
+    const double s = ai + aj;
+    const double tD = s * r;
     if (tD < k.tDmax) {
-        const R inv = drcp(s);
-        const R u = (bi - caj) * inv;
-        const R ts = dmin(u * u, k.tSclamp);
+        const double inv = drcp(s);
+        const double u = (ci - cj) * inv;
+        const double ts = dmin(u * u, k.tSclamp);
         const int kk = (int)tD;
         const int l = (int)ts;
-        const R fD = dfract(tD), fS = dfract(ts);
+        const double fD = dfract(tD), fS = dfract(ts);
         // rows below K come from LDS; the clamped LDS read is always in
         // bounds and is replaced for rows >= K - 1
         const int kl = min(kk, k.K - 2);
-        const unsigned ob = __umul24((unsigned)kl, (unsigned)(S * sizeof(R))) + ((unsigned)l * (unsigned)sizeof(R));
-        const R *t = reinterpret_cast<const R *>(reinterpret_cast<const char *>(tab) + ob);
-        R p00 = t[0], p01 = t[1], p10 = t[S], p11 = t[S + 1];
+        const double *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
+        double p00 = t[0], p01 = t[1], p10 = t[S], p11 = t[S + 1];
         // keep the LDS reads unconditional: without this the compiler folds
         // the two sources into one FLAT load
         asm("" : "+v"(p00), "+v"(p01), "+v"(p10), "+v"(p11));
         if (kk >= k.K - 1) {
-            const R *t0 = tabg + (int64_t)kk * nS + l;
+            const double *t0 = tabg + (int64_t)kk * nS + l;
             p00 = t0[0];
             p01 = t0[1];
             p10 = t0[nS];
             p11 = t0[nS + 1];
         }
-        const R d0 = p01 - p00, d1 = p11 - p10;
-        const R lo = p00 + fS * d0, hi = p10 + fS * d1;
-        const R gD = hi - lo;
-        phi = lo + fD * gD;
-        if (ADJ) {
-            const R gS = d0 + fD * (d1 - d0);
-            // gD r + gS u inv^2 4 csig a_j;  for q_j the sigma term flips sign and a_j -> a_i
-            const R X = gD * r;
-            const R Y = (gS * (u * inv)) * (inv * k.c4);
-            dqi = X + Y * aj;
-            if (JSIDE) dqj = X - Y * ai;
-        }
+        bilinear<double, ADJ, JSIDE>(p00, p01, p10, p11, fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi, dqj);
     } else {
-        // a private copy keeps these rare-branch products from being hoisted
-        R ajx = aj;
-        asm("" : "+v"(ajx));
-        const R pi = ai * ai, pj = ajx * ajx, pp = pi + pj;
-        phi = -k.casym * drcp(m * m * m * pi * pj * pp);
-        if (ADJ) {
-            const R rp = drcp(pp);
-            dqi = -phi * ((R)2 * drcp(ai) + (R)2 * ai * rp);
-            if (JSIDE) dqj = -phi * ((R)2 * drcp(ajx) + (R)2 * ajx * rp);
+        asymptote<double, ADJ, JSIDE>(k, m, ai, aj, phi, dqi, dqj);
+    }
+}
+
+// FP32 form: ci = 2 csig a_i, so u = ci / s - csig in one FMA (cj unused).
+// The LDS rows are read and interpolated for every pair; one compare
+// (t_D >= K - 1) sends the pairs beyond them to a second pass with the
+// global table or the asymptote, which few pairs take.
+template <bool ADJ, bool JSIDE, int NSIG>
+__device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *tab, const float *__restrict__ tabg,
+                                          float m, float ai, float ci, float aj, float cj, float &phi, float &dqi,
+                                          float &dqj)
+{
+    (void)cj;
+    const int S = NSIG ? NSIG + 1 : k.S;
+    const int nS = NSIG ? NSIG : k.nS;
+    const float r = dsqrt(m);
+    const float s = ai + aj;
+    const float tD = s * r;
+    const float inv = drcp(s);
+    const float u = fmaf(ci, inv, -k.csig);
+    const float ts = dmin(u * u, k.tSclamp);
+    const int kk = (int)tD;
+    const int l = (int)ts;
+    const float fD = dfract(tD), fS = dfract(ts);
+    // the clamped LDS read is always in bounds
+    const int kl = min(kk, k.K - 2);
+    const float *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
+    float p00 = t[0], p01 = t[1], p10 = t[S], p11 = t[S + 1];
+    asm("" : "+v"(p00), "+v"(p01), "+v"(p10), "+v"(p11));
+    bilinear<float, ADJ, JSIDE>(p00, p01, p10, p11, fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi, dqj);
+    if (tD >= k.tDlds) {
+        if (tD < k.tDmax) {
+            const float *t0 = tabg + (int64_t)kk * nS + l;
+            bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi,
+                                        dqj);
+        } else {
+            asymptote<float, ADJ, JSIDE>(k, m, ai, aj, phi, dqi, dqj);
         }
     }
 }
 
-// One 64-step ring of an off-diagonal tile against one image shift: every
-// lane meets every j of the tile; the j values and the j-side sums rotate
-// with the records.  MASK applies the distance cut pair by pair (only for
-// tiles that straddle it).
+// i-side constant of the sigma argument: b_i (FP64) or 2 csig a_i (FP32).
+__device__ inline double ci_of(const PairK<double> &, double a, double b) { return b; }
+__device__ inline float ci_of(const PairK<float> &k, float a, float) { return (2.0f * k.csig) * a; }
+// j-side constant: csig a_j (FP64), unused in FP32.
+__device__ inline double cj_of(const PairK<double> &k, double a) { return k.csig * a; }
+__device__ inline float cj_of(const PairK<float> &, float) { return 0.0f; }
+
 // Kahan-compensated sum step: s + y with the running error in c.
 template <typename R>
 __device__ __forceinline__ void kadd(R &sum, R &c, R y)
@@ -444,20 +524,35 @@ __device__ __forceinline__ void kadd(R &sum, R &c, R y)
     sum = t1;
 }
 
+// One 64-step ring of an off-diagonal tile against one image shift: every
+// lane meets every j of the tile; the j values and the j-side sums rotate
+// with the records.  MASK applies the distance cut pair by pair (only for
+// tiles that straddle it).  NORM (FP32 on cubic grids) takes the squared
+// distance from the exact integer form of dist2n, with |x_j|^2 rotating
+// along.
 template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, bool CUBIC>
 __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm, R sxa,
-                                       R sya, R sza, R aia, R bia, R nia, R sxb, R syb, R szb, R aib, R bib, R nib,
-                                       R xj, R yj, R zj, R aj, R nj, R &acca, R &accqa, R &accb, R &accqb, R &accj,
-                                       R &accqj)
+                                       R sya, R sza, R aia, R cia, R nia, R sxb, R syb, R szb, R aib, R cib, R nib,
+                                       R xj, R yj, R zj, R wj, R aj, R nj, R &acca, R &accqa, R &accb, R &accqb,
+                                       R &accj, R &accqj)
 {
+    constexpr bool NORM = CUBIC && sizeof(R) == 4;
+    const R mxa = -2 * sxa, mya = -2 * sya, mza = -2 * sza, wa = sxa * sxa + sya * sya + sza * sza;
+    const R mxb = -2 * sxb, myb = -2 * syb, mzb = -2 * szb, wb = sxb * sxb + syb * syb + szb * szb;
     R ca = 0, cqa = 0, cb = 0, cqb = 0, cj = 0, cqj = 0;  // Kahan terms (KAHAN only)
     for (int st = 0; st < 64; ++st) {
-        const R ma = dist2<R, CUBIC>(kc, sxa - xj, sya - yj, sza - zj);
-        const R mb = dist2<R, CUBIC>(kc, sxb - xj, syb - yj, szb - zj);
-        const R caj = kc.csig * aj;
+        R ma, mb;
+        if (NORM) {
+            ma = (R)dist2n((float)mxa, (float)mya, (float)mza, (float)(wa + wj), (float)xj, (float)yj, (float)zj);
+            mb = (R)dist2n((float)mxb, (float)myb, (float)mzb, (float)(wb + wj), (float)xj, (float)yj, (float)zj);
+        } else {
+            ma = dist2<R, CUBIC>(kc, sxa - xj, sya - yj, sza - zj);
+            mb = dist2<R, CUBIC>(kc, sxb - xj, syb - yj, szb - zj);
+        }
+        const R cj_ = cj_of(kc, aj);
         R pa, qa = 0, ja = 0, pb, qb = 0, jb = 0;
-        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, ma, aia, bia, aj, caj, pa, qa, ja);
-        pair_eval<R, ADJ, true, NSIG>(kc, tab, tabg, mb, aib, bib, aj, caj, pb, qb, jb);
+        pair_eval<ADJ, true, NSIG>(kc, tab, tabg, ma, aia, cia, aj, cj_, pa, qa, ja);
+        pair_eval<ADJ, true, NSIG>(kc, tab, tabg, mb, aib, cib, aj, cj_, pb, qb, jb);
         R wja = nj, wjb = nj, wia = nia, wib = nib;
         if (MASK) {
             wja = (ma <= rcm) ? nj : (R)0;
@@ -487,6 +582,7 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
         xj = wrot(xj);
         yj = wrot(yj);
         zj = wrot(zj);
+        if (NORM) wj = wrot(wj);
         aj = wrot(aj);
         nj = wrot(nj);
         accj = wrot(accj);
@@ -552,14 +648,19 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                                                             double *__restrict__ ipart, R *__restrict__ jpart)
 {
     using Rec = typename RecOf<R>::T;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *tab = reinterpret_cast<R *>(smem_raw);
-    R *red = tab + A.K * A.S;  // [kWaves][NJ][64] j-side sums of one tile
-    int *s_item = reinterpret_cast<int *>(red + kWaves * A.NJ * 64);
+    constexpr int NJc = 1 + (IMG ? 1 : 0) + (ADJ ? 1 : 0);
+    constexpr bool NORM = CUBIC && sizeof(R) == 4;
+    // static LDS: the table rows (K x S, row stride S = n_sigma + 1), the
+    // j-side sums of one tile from every wavefront, the work-item slot
+    __shared__ __align__(16) R tab[tab_elems<R>(NJc)];
+    __shared__ R red[kWaves * NJc * 64];
+    __shared__ int s_item_v;
+    int *s_item = &s_item_v;
 
     const int nS = A.nS;
     PairK<R> kc;
     kc.tDmax = (R)A.tDmax;
+    kc.tDlds = (R)(A.K - 1);
     kc.tSclamp = (R)A.tSclamp;
     kc.csig = (R)A.csig;
     kc.c4 = (R)(4.0 * A.csig);
@@ -613,6 +714,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
         const bool acta = ila < N, actb = ilb < N;
         const Rec Ia = P[acta ? ila : N - 1], Ib = P[actb ? ilb : N - 1];
         const R nia = acta ? Ia.n : (R)0, nib = actb ? Ib.n : (R)0;
+        const R cia = ci_of(kc, Ia.a, Ia.b), cib = ci_of(kc, Ib.a, Ib.b);
 
         double Sc_a = 0.0, SL_a = 0.0, Sq_a = 0.0, Sc_b = 0.0, SL_b = 0.0, Sq_b = 0.0;
         const int nimg = IMG ? A.nimg : 1;
@@ -634,6 +736,8 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                     szb -= mz;
                     home = (L == A.home);
                 }
+                const R mxa = -2 * sxa, mya = -2 * sya, mza = -2 * sza, wa = sxa * sxa + sya * sya + sza * sza;
+                const R mxb = -2 * sxb, myb = -2 * syb, mzb = -2 * szb, wb = sxb * sxb + syb * syb + szb * szb;
                 Rec Jn = P[j0];
                 for (int jr = j0; jr < j1; jr += kRun) {
                     const int je = min(j1, jr + kRun);
@@ -641,17 +745,25 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                     for (int j = jr; j < je; ++j) {
                         const Rec J = Jn;
                         Jn = P[min(j + 1, j1 - 1)];  // prefetch the next record (wave-uniform)
-                        const R ma = dist2<R, CUBIC>(kc, sxa - J.x, sya - J.y, sza - J.z);
-                        const R mb = dist2<R, CUBIC>(kc, sxb - J.x, syb - J.y, szb - J.z);
+                        R ma, mb;
+                        if (NORM) {
+                            ma = (R)dist2n((float)mxa, (float)mya, (float)mza, (float)(wa + J.w), (float)J.x,
+                                           (float)J.y, (float)J.z);
+                            mb = (R)dist2n((float)mxb, (float)myb, (float)mzb, (float)(wb + J.w), (float)J.x,
+                                           (float)J.y, (float)J.z);
+                        } else {
+                            ma = dist2<R, CUBIC>(kc, sxa - J.x, sya - J.y, sza - J.z);
+                            mb = dist2<R, CUBIC>(kc, sxb - J.x, syb - J.y, szb - J.z);
+                        }
                         R wa = (ma > (R)0) ? J.n : (R)0, wb = (mb > (R)0) ? J.n : (R)0;
                         if (IMG) {
                             wa = (ma <= rcm) ? wa : (R)0;
                             wb = (mb <= rcm) ? wb : (R)0;
                         }
-                        const R caj = kc.csig * J.a;
+                        const R cj = cj_of(kc, J.a);
                         R pa, qa = 0, pb, qb = 0, unused;
-                        pair_eval<R, ADJ, false, NSIG>(kc, tab, tabg, ma, Ia.a, Ia.b, J.a, caj, pa, qa, unused);
-                        pair_eval<R, ADJ, false, NSIG>(kc, tab, tabg, mb, Ib.a, Ib.b, J.a, caj, pb, qb, unused);
+                        pair_eval<ADJ, false, NSIG>(kc, tab, tabg, ma, Ia.a, cia, J.a, cj, pa, qa, unused);
+                        pair_eval<ADJ, false, NSIG>(kc, tab, tabg, mb, Ib.a, cib, J.a, cj, pb, qb, unused);
                         if (KAHAN) {
                             R y = wa * pa - cma, t = acca + y;
                             cma = (t - acca) - y;
@@ -734,13 +846,13 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                     R accj = 0, accqj = 0, acca = 0, accqa = 0, accb = 0, accqb = 0;
                     const R nj0 = jv ? Jr.n : (R)0;
                     if (masked)
-                        ring64<R, ADJ, true, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, Ia.b, nia, sxb, syb,
-                                                          szb, Ib.a, Ib.b, nib, Jr.x, Jr.y, Jr.z, Jr.a, nj0, acca,
-                                                          accqa, accb, accqb, accj, accqj);
+                        ring64<R, ADJ, true, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, cia, nia, sxb,
+                                                                 syb, szb, Ib.a, cib, nib, Jr.x, Jr.y, Jr.z, Jr.w, Jr.a,
+                                                                 nj0, acca, accqa, accb, accqb, accj, accqj);
                     else
-                        ring64<R, ADJ, false, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, Ia.b, nia, sxb,
-                                                           syb, szb, Ib.a, Ib.b, nib, Jr.x, Jr.y, Jr.z, Jr.a, nj0, acca,
-                                                           accqa, accb, accqb, accj, accqj);
+                        ring64<R, ADJ, false, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, cia, nia, sxb,
+                                                                  syb, szb, Ib.a, cib, nib, Jr.x, Jr.y, Jr.z, Jr.w, Jr.a,
+                                                                  nj0, acca, accqa, accb, accqb, accj, accqj);
                     if (home) {
                         Sc_a += (double)acca;
                         Sc_b += (double)accb;
@@ -757,14 +869,14 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                     }
                 }
                 // j-side sums of the tile: 16 wavefronts in a fixed order
-                red[(w * A.NJ + 0) * 64 + lane] = jSc;
-                if (IMG) red[(w * A.NJ + iS0L) * 64 + lane] = jSL;
-                if (ADJ) red[(w * A.NJ + iSq) * 64 + lane] = jSq;
+                red[(w * NJc + 0) * 64 + lane] = jSc;
+                if (IMG) red[(w * NJc + iS0L) * 64 + lane] = jSL;
+                if (ADJ) red[(w * NJc + iSq) * 64 + lane] = jSq;
                 __syncthreads();
-                if (threadIdx.x < A.NJ * 64) {
+                if (threadIdx.x < NJc * 64) {
                     const int a = threadIdx.x >> 6, jl = threadIdx.x & 63;
                     R sum = 0;
-                    for (int v = 0; v < kWaves; ++v) sum += red[(v * A.NJ + a) * 64 + jl];
+                    for (int v = 0; v < kWaves; ++v) sum += red[(v * NJc + a) * 64 + jl];
                     if (t0 + jl < J1) jpart[a * A.jstride + slot * A.JC + (t0 + jl - J0)] = sum;
                 }
                 __syncthreads();
@@ -1030,6 +1142,7 @@ struct Plan {
     std::vector<Seg> segs;
     std::vector<int> imgs;  // 4 ints per image
     int nimg = 1, home = 0;
+    int mimg[3] = {0, 0, 0};  // image range per axis (0 on open axes)
     bool img = false;
     int JC = 8192;
     int NI = 1, NJ = 1;
@@ -1091,6 +1204,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         int per = a == 0 ? P->segs[0].px : a == 1 ? P->segs[0].py : P->segs[0].pz;
         if (o->image_max[a] < 0) return fail(VDW_EINVAL, "image_max must be >= 0");
         m[a] = per ? o->image_max[a] : 0;
+        P->mimg[a] = m[a];
     }
     P->imgs.clear();
     P->nimg = 0;
@@ -1178,17 +1292,11 @@ struct PairPtrs {
 template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC>
 int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
-    auto k = pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC>;
-    if (attr_only) {
-        // raises the dynamic-LDS limit where the runtime enforces one (done
-        // once per evaluation, outside any stream capture); a failure here
-        // surfaces at the launch
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        return VDW_OK;
-    }
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kPairThreads), lds, s, a, (const typename RecOf<R>::T *)p.recs, p.segs,
-                       p.hdr, p.counter, (const R *)p.tabg, p.imgs, p.rowoff, p.ipart, (R *)p.jpart);
+    // the kernel's LDS is static (kLdsBytes); nothing to set up
+    if (attr_only) return VDW_OK;
+    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC>), dim3(grid), dim3(kPairThreads), lds, s, a,
+                       (const typename RecOf<R>::T *)p.recs, p.segs, p.hdr, p.counter, (const R *)p.tabg, p.imgs,
+                       p.rowoff, p.ipart, (R *)p.jpart);
     VDW_HIP(hipGetLastError());
     return VDW_OK;
 }
@@ -1259,16 +1367,20 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     const Plan &P = E->P;
     if (ws_bytes < P.L.total) return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
     E->ws = (char *)ws;
-    const size_t esz = E->fp64 ? sizeof(double) : sizeof(float);
     const int S = tp->n_sigma + 1;
-    const size_t red_bytes = (size_t)kWaves * P.NJ * 64 * esz;  // j-side tile sums
-    const size_t lds_cap = dev.lds_per_block > 256 + red_bytes ? dev.lds_per_block - 256 - red_bytes : 0;
-    int K = (int)(lds_cap / (S * esz));
+    if (dev.lds_per_block < (size_t)kLdsBytes)
+        return fail(VDW_EUNSUPPORTED, "the pair kernel needs %d bytes of LDS per workgroup (device: %zu)", kLdsBytes,
+                    dev.lds_per_block);
+    // table rows that fit in the kernel's static LDS next to its reduction buffer
+    const int cap = E->fp64 ? tab_elems<double>(P.NJ) : tab_elems<float>(P.NJ);
+    int K = cap / S;
     if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
     if (K > tp->n_D) K = tp->n_D;
     if (K < 2) K = 2;  // the kernel reads a clamped LDS row unconditionally
+    if (K * S > cap) return fail(VDW_EINVAL, "n_sigma = %d is too large for the LDS table (at most %d)", tp->n_sigma,
+                                 cap / 2 - 1);
     E->K = K;
-    E->lds = (size_t)K * S * esz + red_bytes + 16;
+    E->lds = 0;
     E->grid = o->grid_blocks > 0 ? o->grid_blocks : dev.cus;
     E->dD = tp->D_max / (tp->n_D - 1);
     E->Dmax = tp->D_max;
@@ -1294,9 +1406,18 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.NJ = P.NJ;
     pa.istride = P.L.slots * kBI;
     pa.jstride = P.L.slots * (int64_t)P.JC;
+    // cubic grids take the exact integer form of the squared distance: its
+    // partial sums stay below 12 c^2 for coordinates |c| <= c_max (image
+    // shifts included), exact in FP32 while 12 c_max^2 < 2^24
     E->cubic = 1;
-    for (int b = 0; b < B; ++b)
-        if (!(P.segs[b].hx == P.segs[b].hy && P.segs[b].hx == P.segs[b].hz)) E->cubic = 0;
+    double cmax = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const Seg &g = P.segs[b];
+        if (!(g.hx == g.hy && g.hx == g.hz)) E->cubic = 0;
+        const int n3[3] = {g.nx, g.ny, g.nz};
+        for (int a = 0; a < 3; ++a) cmax = fmax(cmax, (double)n3[a] * (1 + P.mimg[a]));
+    }
+    if (12.0 * cmax * cmax >= 16777216.0) E->cubic = 0;
     PairPtrs none{};
     return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->cubic, pa, none, E->grid, E->lds, nullptr,
                        true);
