@@ -33,7 +33,7 @@ PEAK_FP32_TFLOPS = 157.3
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
-TRAFFIC_BYTES = {"kr": (1028704.6875 * 2.0 + 961572.15625) * 1024}
+TRAFFIC_BYTES = {}
 
 
 def parse():

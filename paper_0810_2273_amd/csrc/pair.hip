@@ -47,7 +47,6 @@ constexpr int kCompactBlock = 1024;  // brick-order positions per count/scatter 
 constexpr int kCompactThreads = 256;  // 4 positions (one brick row) per thread
 constexpr int kPairThreads = 1024;    // threads of a pair workgroup
 constexpr int kWaves = kPairThreads / 64;
-constexpr int kBI = 2 * kPairThreads; // i-points per row block (two per lane)
 constexpr int kFinThreads = 256;      // points per finalize block
 constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 carry (diagonal items)
 constexpr int kLdsBytes = 160 * 1024; // LDS of one gfx950 workgroup
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(const Seg *__res
 // total appended), then the per-density offsets the later kernels use.
 __global__ __launch_bounds__(1024) void scan_kernel(int64_t *__restrict__ counts, int64_t nblocks,
                                                     Seg *__restrict__ segs, int B, int64_t *__restrict__ hdr,
-                                                    int64_t *__restrict__ rowoff, int64_t JC)
+                                                    int64_t *__restrict__ rowoff, int64_t JC, int64_t BI)
 {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
@@ -203,12 +202,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t *__restrict__ counts
             int64_t first = g.t_off / kCompactBlock, last = (g.t_off + g.T) / kCompactBlock;
             g.p_off = counts[first];
             g.N = counts[last] - counts[first];
-            g.nIB = (g.N + kBI - 1) / kBI;
-            // row I: one diagonal item, then ceil((N - (I+1) kBI) / JC) chunks
+            g.nIB = (g.N + BI - 1) / BI;
+            // row I: one diagonal item, then ceil((N - (I+1) BI) / JC) chunks
             int64_t items = 0;
             for (int64_t I = 0; I < g.nIB; ++I) {
                 rowoff[g.row_base + I] = items;
-                int64_t rest = g.N - (I + 1) * kBI;
+                int64_t rest = g.N - (I + 1) * BI;
                 items += 1 + (rest > 0 ? (rest + JC - 1) / JC : 0);
             }
             rowoff[g.row_base + g.nIB] = items;
@@ -312,6 +311,7 @@ struct PairArgs {
     int B;
     int nD, nS, S, K;   // S: LDS row stride (n_sigma + 1); K: rows held in LDS
     int JC;             // j-points per off-diagonal item (multiple of 64)
+    int BI;             // i-points per row block (IPL x kPairThreads of the variant)
     double tDmax;       // n_D - 1: table branch iff t_D = D / dD < n_D - 1
     double tSclamp;     // largest value below n_sigma - 1 (sigma index clamp)
     double csig;        // sqrt(n_sigma - 1)
@@ -487,21 +487,24 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
     const float tD = s * r;
     const float inv = drcp(s);
     const float u = fmaf(ci, inv, -k.csig);
-    const float ts = dmin(u * u, k.tSclamp);
+    // t_s < n_sigma (|delta| < 1 up to rounding), so l + 1 <= n_sigma: the
+    // LDS rows carry a column n_sigma that continues the last cell linearly,
+    // which is the interpolant's own extrapolation beyond sigma = 1
+    const float ts = u * u;
     const int kk = (int)tD;
     const int l = (int)ts;
     const float fD = dfract(tD), fS = dfract(ts);
     // the clamped LDS read is always in bounds
     const int kl = min(kk, k.K - 2);
     const float *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
-    float p00 = t[0], p01 = t[1], p10 = t[S], p11 = t[S + 1];
-    asm("" : "+v"(p00), "+v"(p01), "+v"(p10), "+v"(p11));
-    bilinear<float, ADJ, JSIDE>(p00, p01, p10, p11, fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi, dqj);
+    bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi, dqj);
     if (tD >= k.tDlds) {
         if (tD < k.tDmax) {
-            const float *t0 = tabg + (int64_t)kk * nS + l;
-            bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi,
-                                        dqj);
+            // global rows have no extra column: last cell and its fraction
+            const int lg = min(l, nS - 2);
+            const float *t0 = tabg + (int64_t)kk * nS + lg;
+            bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, k.c4, ai,
+                                        aj, phi, dqi, dqj);
         } else {
             asymptote<float, ADJ, JSIDE>(k, m, ai, aj, phi, dqi, dqj);
         }
@@ -525,59 +528,66 @@ __device__ __forceinline__ void kadd(R &sum, R &c, R y)
 }
 
 // One 64-step ring of an off-diagonal tile against one image shift: every
-// lane meets every j of the tile; the j values and the j-side sums rotate
-// with the records.  MASK applies the distance cut pair by pair (only for
-// tiles that straddle it).  NORM (FP32 on cubic grids) takes the squared
-// distance from the exact integer form of dist2n, with |x_j|^2 rotating
-// along.
-template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, bool CUBIC>
-__device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm, R sxa,
-                                       R sya, R sza, R aia, R cia, R nia, R sxb, R syb, R szb, R aib, R cib, R nib,
-                                       R xj, R yj, R zj, R wj, R aj, R nj, R &acca, R &accqa, R &accb, R &accqb,
-                                       R &accj, R &accqj)
+// lane meets every j of the tile with each of its IPL i-points; the j values
+// and the j-side sums rotate with the records.  MASK applies the distance cut
+// pair by pair (only for tiles that straddle it).  NORM (FP32 on cubic
+// grids) takes the squared distance from the exact integer form of dist2n,
+// with |x_j|^2 rotating along.
+template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, bool CUBIC, int IPL>
+__device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm,
+                                       const R (&sx)[IPL], const R (&sy)[IPL], const R (&sz)[IPL], const R (&ai)[IPL],
+                                       const R (&ci)[IPL], const R (&ni)[IPL], R xj, R yj, R zj, R wj, R aj, R nj,
+                                       R (&acc)[IPL], R (&accq)[IPL], R &accj, R &accqj)
 {
     constexpr bool NORM = CUBIC && sizeof(R) == 4;
-    const R mxa = -2 * sxa, mya = -2 * sya, mza = -2 * sza, wa = sxa * sxa + sya * sya + sza * sza;
-    const R mxb = -2 * sxb, myb = -2 * syb, mzb = -2 * szb, wb = sxb * sxb + syb * syb + szb * szb;
-    R ca = 0, cqa = 0, cb = 0, cqb = 0, cj = 0, cqj = 0;  // Kahan terms (KAHAN only)
+    R mx[IPL], my[IPL], mz[IPL], wi[IPL], ca[IPL], cq[IPL];
+#pragma unroll
+    for (int p = 0; p < IPL; ++p) {
+        mx[p] = -2 * sx[p];
+        my[p] = -2 * sy[p];
+        mz[p] = -2 * sz[p];
+        wi[p] = sx[p] * sx[p] + sy[p] * sy[p] + sz[p] * sz[p];
+        ca[p] = 0;  // Kahan terms (KAHAN only)
+        cq[p] = 0;
+    }
+    R cj = 0, cqj = 0;
     for (int st = 0; st < 64; ++st) {
-        R ma, mb;
-        if (NORM) {
-            ma = (R)dist2n((float)mxa, (float)mya, (float)mza, (float)(wa + wj), (float)xj, (float)yj, (float)zj);
-            mb = (R)dist2n((float)mxb, (float)myb, (float)mzb, (float)(wb + wj), (float)xj, (float)yj, (float)zj);
-        } else {
-            ma = dist2<R, CUBIC>(kc, sxa - xj, sya - yj, sza - zj);
-            mb = dist2<R, CUBIC>(kc, sxb - xj, syb - yj, szb - zj);
-        }
         const R cj_ = cj_of(kc, aj);
-        R pa, qa = 0, ja = 0, pb, qb = 0, jb = 0;
-        pair_eval<ADJ, true, NSIG>(kc, tab, tabg, ma, aia, cia, aj, cj_, pa, qa, ja);
-        pair_eval<ADJ, true, NSIG>(kc, tab, tabg, mb, aib, cib, aj, cj_, pb, qb, jb);
-        R wja = nj, wjb = nj, wia = nia, wib = nib;
-        if (MASK) {
-            wja = (ma <= rcm) ? nj : (R)0;
-            wjb = (mb <= rcm) ? nj : (R)0;
-            wia = (ma <= rcm) ? nia : (R)0;
-            wib = (mb <= rcm) ? nib : (R)0;
+        R sj = 0, sqj = 0;  // j-side terms of this step (KAHAN only)
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            R m;
+            if (NORM)
+                m = (R)dist2n((float)mx[p], (float)my[p], (float)mz[p], (float)(wi[p] + wj), (float)xj, (float)yj,
+                              (float)zj);
+            else
+                m = dist2<R, CUBIC>(kc, sx[p] - xj, sy[p] - yj, sz[p] - zj);
+            R ph, q = 0, jq = 0;
+            pair_eval<ADJ, true, NSIG>(kc, tab, tabg, m, ai[p], ci[p], aj, cj_, ph, q, jq);
+            R wjp = nj, wip = ni[p];
+            if (MASK) {
+                wjp = (m <= rcm) ? nj : (R)0;
+                wip = (m <= rcm) ? ni[p] : (R)0;
+            }
+            if (KAHAN) {
+                kadd(acc[p], ca[p], wjp * ph);
+                sj = fma(wip, ph, sj);
+                if (ADJ) {
+                    kadd(accq[p], cq[p], wjp * q);
+                    sqj = fma(wip, jq, sqj);
+                }
+            } else {
+                acc[p] = fma(wjp, ph, acc[p]);
+                accj = fma(wip, ph, accj);
+                if (ADJ) {
+                    accq[p] = fma(wjp, q, accq[p]);
+                    accqj = fma(wip, jq, accqj);
+                }
+            }
         }
         if (KAHAN) {
-            kadd(acca, ca, wja * pa);
-            kadd(accb, cb, wjb * pb);
-            kadd(accj, cj, fma(wib, pb, wia * pa));
-            if (ADJ) {
-                kadd(accqa, cqa, wja * qa);
-                kadd(accqb, cqb, wjb * qb);
-                kadd(accqj, cqj, fma(wib, jb, wia * ja));
-            }
-        } else {
-            acca = fma(wja, pa, acca);
-            accb = fma(wjb, pb, accb);
-            accj = fma(wib, pb, fma(wia, pa, accj));
-            if (ADJ) {
-                accqa = fma(wja, qa, accqa);
-                accqb = fma(wjb, qb, accqb);
-                accqj = fma(wib, jb, fma(wia, ja, accqj));
-            }
+            kadd(accj, cj, sj);
+            if (ADJ) kadd(accqj, cqj, sqj);
         }
         xj = wrot(xj);
         yj = wrot(yj);
@@ -594,11 +604,12 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
     }
     if (KAHAN) {
         // fold the compensation into the sums
-        acca -= ca;
-        accb -= cb;
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            acc[p] -= ca[p];
+            accq[p] -= cq[p];
+        }
         accj -= cj;
-        accqa -= cqa;
-        accqb -= cqb;
         accqj -= cqj;
     }
 }
@@ -639,7 +650,7 @@ __device__ inline void box_dist2(const R *bi, const R *bj, R sx, R sy, R sz, R w
 // Pointers are separate __restrict__ parameters so the compiler knows the
 // records, segments and table are not written during the kernel and can
 // fetch wave-uniform records with scalar loads.
-template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC>
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL>
 __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const typename RecOf<R>::T *__restrict__ recs,
                                                             const Seg *__restrict__ segs,
                                                             const int64_t *__restrict__ hdr, int *__restrict__ counter,
@@ -672,6 +683,8 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
     for (int t = threadIdx.x; t < A.K * nS; t += kPairThreads) {
         int r = t / nS, c = t - r * nS;
         tab[r * A.S + c] = tabg[t];
+        // column n_sigma: linear continuation of the last cell (FP32 form)
+        if (sizeof(R) == 4 && c == nS - 1) tab[r * A.S + nS] = (R)2 * tabg[t] - tabg[t - 1];
     }
     __syncthreads();
 
@@ -709,104 +722,110 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
         const R rcm = (R)(A.rc2 / (sg.hx * sg.hx));  // distance cut in units of h_x^2
         const Rec *__restrict__ P = recs + sg.p_off;
 
-        // two i-points per lane
-        const int ila = I * kBI + w * 128 + lane, ilb = ila + 64;
-        const bool acta = ila < N, actb = ilb < N;
-        const Rec Ia = P[acta ? ila : N - 1], Ib = P[actb ? ilb : N - 1];
-        const R nia = acta ? Ia.n : (R)0, nib = actb ? Ib.n : (R)0;
-        const R cia = ci_of(kc, Ia.a, Ia.b), cib = ci_of(kc, Ib.a, Ib.b);
-
-        double Sc_a = 0.0, SL_a = 0.0, Sq_a = 0.0, Sc_b = 0.0, SL_b = 0.0, Sq_b = 0.0;
+        // IPL i-points per lane: point p of lane l of wavefront w is number
+        // w (64 IPL) + 64 p + l of the row block
+        constexpr int BI = IPL * kPairThreads;
+        bool act[IPL];
+        Rec Ir[IPL];
+        R ai[IPL], ci[IPL], ni[IPL];
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            const int il = I * BI + w * (64 * IPL) + 64 * p + lane;
+            act[p] = il < N;
+            Ir[p] = P[act[p] ? il : N - 1];
+            ai[p] = Ir[p].a;
+            ci[p] = ci_of(kc, Ir[p].a, Ir[p].b);
+            ni[p] = act[p] ? Ir[p].n : (R)0;
+        }
+        double Sc[IPL], SL[IPL], Sq[IPL];
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) Sc[p] = SL[p] = Sq[p] = 0.0;
         const int nimg = IMG ? A.nimg : 1;
 
         if (c == 0) {
             // diagonal item: ordered pairs inside the row block, j through scalar loads
-            const int j0 = I * kBI, j1 = min(N, j0 + kBI);
+            const int j0 = I * BI, j1 = min(N, j0 + BI);
             for (int L = 0; L < nimg; ++L) {
-                R sxa = Ia.x, sya = Ia.y, sza = Ia.z, sxb = Ib.x, syb = Ib.y, szb = Ib.z;
+                R sx[IPL], sy[IPL], sz[IPL], mx[IPL], my[IPL], mz[IPL], wi[IPL];
                 bool home = true;
+                R lx = 0, ly = 0, lz = 0;
                 if (IMG) {
-                    const R mx = (R)(imgs[4 * L + 0] * sg.nx), my = (R)(imgs[4 * L + 1] * sg.ny),
-                            mz = (R)(imgs[4 * L + 2] * sg.nz);
-                    sxa -= mx;
-                    sya -= my;
-                    sza -= mz;
-                    sxb -= mx;
-                    syb -= my;
-                    szb -= mz;
+                    lx = (R)(imgs[4 * L + 0] * sg.nx);
+                    ly = (R)(imgs[4 * L + 1] * sg.ny);
+                    lz = (R)(imgs[4 * L + 2] * sg.nz);
                     home = (L == A.home);
                 }
-                const R mxa = -2 * sxa, mya = -2 * sya, mza = -2 * sza, wa = sxa * sxa + sya * sya + sza * sza;
-                const R mxb = -2 * sxb, myb = -2 * syb, mzb = -2 * szb, wb = sxb * sxb + syb * syb + szb * szb;
+#pragma unroll
+                for (int p = 0; p < IPL; ++p) {
+                    sx[p] = Ir[p].x - lx;
+                    sy[p] = Ir[p].y - ly;
+                    sz[p] = Ir[p].z - lz;
+                    mx[p] = -2 * sx[p];
+                    my[p] = -2 * sy[p];
+                    mz[p] = -2 * sz[p];
+                    wi[p] = sx[p] * sx[p] + sy[p] * sy[p] + sz[p] * sz[p];
+                }
                 Rec Jn = P[j0];
                 for (int jr = j0; jr < j1; jr += kRun) {
                     const int je = min(j1, jr + kRun);
-                    R acca = 0, accqa = 0, accb = 0, accqb = 0, cma = 0, cmb = 0;
+                    R acc[IPL], accq[IPL], cm[IPL];
+#pragma unroll
+                    for (int p = 0; p < IPL; ++p) acc[p] = accq[p] = cm[p] = 0;
                     for (int j = jr; j < je; ++j) {
                         const Rec J = Jn;
                         Jn = P[min(j + 1, j1 - 1)];  // prefetch the next record (wave-uniform)
-                        R ma, mb;
-                        if (NORM) {
-                            ma = (R)dist2n((float)mxa, (float)mya, (float)mza, (float)(wa + J.w), (float)J.x,
-                                           (float)J.y, (float)J.z);
-                            mb = (R)dist2n((float)mxb, (float)myb, (float)mzb, (float)(wb + J.w), (float)J.x,
-                                           (float)J.y, (float)J.z);
-                        } else {
-                            ma = dist2<R, CUBIC>(kc, sxa - J.x, sya - J.y, sza - J.z);
-                            mb = dist2<R, CUBIC>(kc, sxb - J.x, syb - J.y, szb - J.z);
-                        }
-                        R wa = (ma > (R)0) ? J.n : (R)0, wb = (mb > (R)0) ? J.n : (R)0;
-                        if (IMG) {
-                            wa = (ma <= rcm) ? wa : (R)0;
-                            wb = (mb <= rcm) ? wb : (R)0;
-                        }
                         const R cj = cj_of(kc, J.a);
-                        R pa, qa = 0, pb, qb = 0, unused;
-                        pair_eval<ADJ, false, NSIG>(kc, tab, tabg, ma, Ia.a, cia, J.a, cj, pa, qa, unused);
-                        pair_eval<ADJ, false, NSIG>(kc, tab, tabg, mb, Ib.a, cib, J.a, cj, pb, qb, unused);
-                        if (KAHAN) {
-                            R y = wa * pa - cma, t = acca + y;
-                            cma = (t - acca) - y;
-                            acca = t;
-                            y = wb * pb - cmb;
-                            t = accb + y;
-                            cmb = (t - accb) - y;
-                            accb = t;
-                        } else {
-                            acca += wa * pa;
-                            accb += wb * pb;
-                        }
-                        if (ADJ) {
-                            accqa += wa * qa;
-                            accqb += wb * qb;
+#pragma unroll
+                        for (int p = 0; p < IPL; ++p) {
+                            R m;
+                            if (NORM)
+                                m = (R)dist2n((float)mx[p], (float)my[p], (float)mz[p], (float)(wi[p] + J.w),
+                                              (float)J.x, (float)J.y, (float)J.z);
+                            else
+                                m = dist2<R, CUBIC>(kc, sx[p] - J.x, sy[p] - J.y, sz[p] - J.z);
+                            R wt = (m > (R)0) ? J.n : (R)0;
+                            if (IMG) wt = (m <= rcm) ? wt : (R)0;
+                            R ph, q = 0, unused;
+                            pair_eval<ADJ, false, NSIG>(kc, tab, tabg, m, ai[p], ci[p], J.a, cj, ph, q, unused);
+                            if (KAHAN) {
+                                R y = wt * ph - cm[p], t = acc[p] + y;
+                                cm[p] = (t - acc[p]) - y;
+                                acc[p] = t;
+                            } else {
+                                acc[p] += wt * ph;
+                            }
+                            if (ADJ) accq[p] += wt * q;
                         }
                     }
-                    if (home) {
-                        Sc_a += (double)acca - (double)cma;
-                        Sc_b += (double)accb - (double)cmb;
-                    } else {
-                        SL_a += (double)acca - (double)cma;
-                        SL_b += (double)accb - (double)cmb;
-                    }
-                    if (ADJ) {
-                        Sq_a += (double)accqa;
-                        Sq_b += (double)accqb;
+#pragma unroll
+                    for (int p = 0; p < IPL; ++p) {
+                        if (home) Sc[p] += (double)acc[p] - (double)cm[p];
+                        else SL[p] += (double)acc[p] - (double)cm[p];
+                        if (ADJ) Sq[p] += (double)accq[p];
                     }
                 }
             }
         } else {
             // off-diagonal item: both orders of every pair, j tiles rotating through the lanes
-            const int J0 = (I + 1) * kBI + (c - 1) * A.JC, J1 = min(N, J0 + A.JC);
+            const int J0 = (I + 1) * BI + (c - 1) * A.JC, J1 = min(N, J0 + A.JC);
             const bool prune = IMG && A.rc2 < 1e300;
             R ib[6] = {0, 0, 0, 0, 0, 0};
             if (prune) {
-                // bounding box of this wavefront's i-points (both per lane)
-                ib[0] = __builtin_amdgcn_readfirstlane(wave_min<R>(min(Ia.x, Ib.x)));
-                ib[1] = __builtin_amdgcn_readfirstlane(wave_max<R>(max(Ia.x, Ib.x)));
-                ib[2] = __builtin_amdgcn_readfirstlane(wave_min<R>(min(Ia.y, Ib.y)));
-                ib[3] = __builtin_amdgcn_readfirstlane(wave_max<R>(max(Ia.y, Ib.y)));
-                ib[4] = __builtin_amdgcn_readfirstlane(wave_min<R>(min(Ia.z, Ib.z)));
-                ib[5] = __builtin_amdgcn_readfirstlane(wave_max<R>(max(Ia.z, Ib.z)));
+                // bounding box of this wavefront's i-points
+                R lo[3] = {Ir[0].x, Ir[0].y, Ir[0].z}, hi[3] = {Ir[0].x, Ir[0].y, Ir[0].z};
+#pragma unroll
+                for (int p = 1; p < IPL; ++p) {
+                    lo[0] = min(lo[0], Ir[p].x);
+                    hi[0] = max(hi[0], Ir[p].x);
+                    lo[1] = min(lo[1], Ir[p].y);
+                    hi[1] = max(hi[1], Ir[p].y);
+                    lo[2] = min(lo[2], Ir[p].z);
+                    hi[2] = max(hi[2], Ir[p].z);
+                }
+                for (int a3 = 0; a3 < 3; ++a3) {
+                    ib[2 * a3] = __builtin_amdgcn_readfirstlane(wave_min<R>(lo[a3]));
+                    ib[2 * a3 + 1] = __builtin_amdgcn_readfirstlane(wave_max<R>(hi[a3]));
+                }
             }
             for (int t0 = J0; t0 < J1; t0 += 64) {
                 const int jj = t0 + lane;
@@ -823,50 +842,48 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                 }
                 R jSc = 0, jSL = 0, jSq = 0;
                 for (int L = 0; L < nimg; ++L) {
-                    R sxa = Ia.x, sya = Ia.y, sza = Ia.z, sxb = Ib.x, syb = Ib.y, szb = Ib.z;
+                    R lx = 0, ly = 0, lz = 0;
                     bool home = true, masked = IMG;
                     if (IMG) {
-                        const R mx = (R)(imgs[4 * L + 0] * sg.nx), my = (R)(imgs[4 * L + 1] * sg.ny),
-                                mz = (R)(imgs[4 * L + 2] * sg.nz);
-                        sxa -= mx;
-                        sya -= my;
-                        sza -= mz;
-                        sxb -= mx;
-                        syb -= my;
-                        szb -= mz;
+                        lx = (R)(imgs[4 * L + 0] * sg.nx);
+                        ly = (R)(imgs[4 * L + 1] * sg.ny);
+                        lz = (R)(imgs[4 * L + 2] * sg.nz);
                         home = (L == A.home);
                         if (prune) {
                             // r_i - r_j - L: the j box shifted by +L against the i box
                             R dmin2, dmax2;
-                            box_dist2<R>(ib, jb6, mx, my, mz, kc.wy, kc.wz, dmin2, dmax2);
+                            box_dist2<R>(ib, jb6, lx, ly, lz, kc.wy, kc.wz, dmin2, dmax2);
                             if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
                             masked = dmax2 > rcm;
                         }
                     }
-                    R accj = 0, accqj = 0, acca = 0, accqa = 0, accb = 0, accqb = 0;
+                    R sx[IPL], sy[IPL], sz[IPL], acc[IPL], accq[IPL];
+#pragma unroll
+                    for (int p = 0; p < IPL; ++p) {
+                        sx[p] = Ir[p].x - lx;
+                        sy[p] = Ir[p].y - ly;
+                        sz[p] = Ir[p].z - lz;
+                        acc[p] = accq[p] = 0;
+                    }
+                    R accj = 0, accqj = 0;
                     const R nj0 = jv ? Jr.n : (R)0;
                     if (masked)
-                        ring64<R, ADJ, true, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, cia, nia, sxb,
-                                                                 syb, szb, Ib.a, cib, nib, Jr.x, Jr.y, Jr.z, Jr.w, Jr.a,
-                                                                 nj0, acca, accqa, accb, accqb, accj, accqj);
+                        ring64<R, ADJ, true, KAHAN, NSIG, CUBIC, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
+                                                                      Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
+                                                                      accqj);
                     else
-                        ring64<R, ADJ, false, KAHAN, NSIG, CUBIC>(kc, tab, tabg, rcm, sxa, sya, sza, Ia.a, cia, nia, sxb,
-                                                                  syb, szb, Ib.a, cib, nib, Jr.x, Jr.y, Jr.z, Jr.w, Jr.a,
-                                                                  nj0, acca, accqa, accb, accqb, accj, accqj);
-                    if (home) {
-                        Sc_a += (double)acca;
-                        Sc_b += (double)accb;
-                        jSc += accj;
-                    } else {
-                        SL_a += (double)acca;
-                        SL_b += (double)accb;
-                        jSL += accj;
+                        ring64<R, ADJ, false, KAHAN, NSIG, CUBIC, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
+                                                                       Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
+                                                                       accqj);
+#pragma unroll
+                    for (int p = 0; p < IPL; ++p) {
+                        if (home) Sc[p] += (double)acc[p];
+                        else SL[p] += (double)acc[p];
+                        if (ADJ) Sq[p] += (double)accq[p];
                     }
-                    if (ADJ) {
-                        Sq_a += (double)accqa;
-                        Sq_b += (double)accqb;
-                        jSq += accqj;
-                    }
+                    if (home) jSc += accj;
+                    else jSL += accj;
+                    if (ADJ) jSq += accqj;
                 }
                 // j-side sums of the tile: 16 wavefronts in a fixed order
                 red[(w * NJc + 0) * 64 + lane] = jSc;
@@ -882,17 +899,14 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                 __syncthreads();
             }
         }
-        const int64_t base = slot * kBI + w * 128 + lane;
+        const int64_t base = slot * BI + w * (64 * IPL) + lane;
         const double qscale = sg.hx / A.dD2;  // d/dq = h_x / (2 dD) times the sums above
-        if (acta) {
-            ipart[base] = Sc_a;
-            if (IMG) ipart[iS0L * A.istride + base] = SL_a;
-            if (ADJ) ipart[iSq * A.istride + base] = Sq_a * qscale;
-        }
-        if (actb) {
-            ipart[base + 64] = Sc_b;
-            if (IMG) ipart[iS0L * A.istride + base + 64] = SL_b;
-            if (ADJ) ipart[iSq * A.istride + base + 64] = Sq_b * qscale;
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            if (!act[p]) continue;
+            ipart[base + 64 * p] = Sc[p];
+            if (IMG) ipart[iS0L * A.istride + base + 64 * p] = SL[p];
+            if (ADJ) ipart[iSq * A.istride + base + 64 * p] = Sq[p] * qscale;
         }
     }
 }
@@ -910,7 +924,7 @@ struct FinArgs {
     const void *jpart;
     int jfp64;
     int64_t istride, jstride;
-    int JC, NI, NJ;
+    int JC, BI, NI, NJ;
     int img, adj, self_term;
     const int32_t *gidx;
     const double *n, *q0, *dqdn;
@@ -954,16 +968,16 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         const int iL = 1, iq = F.NI - 1;
         const int64_t *ro = F.rowoff + sg.row_base;
         // as an i-point: the diagonal item and the chunks of its own row block
-        const int64_t Bk = lp / kBI, t = lp - Bk * kBI;
+        const int64_t Bk = lp / F.BI, t = lp - Bk * F.BI;
         for (int64_t it = ro[Bk]; it < ro[Bk + 1]; ++it) {
-            const int64_t k = (sg.slot_base + it) * kBI + t;
+            const int64_t k = (sg.slot_base + it) * F.BI + t;
             S0c += F.ipart[k];
             if (F.img) S0L += F.ipart[iL * F.istride + k];
             if (F.adj) Sq += F.ipart[iq * F.istride + k];
         }
         // as a j-point: one chunk in each earlier row block
         for (int64_t I = 0; I < Bk; ++I) {
-            const int64_t off = lp - (I + 1) * kBI;
+            const int64_t off = lp - (I + 1) * F.BI;
             const int64_t cc = off / F.JC;
             const int64_t k = (sg.slot_base + ro[I] + 1 + cc) * F.JC + (off - cc * F.JC);
             if (F.jfp64) {
@@ -1145,15 +1159,31 @@ struct Plan {
     int mimg[3] = {0, 0, 0};  // image range per axis (0 on open axes)
     bool img = false;
     int JC = 8192;
+    int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
     int NI = 1, NJ = 1;
     Layout L;
 };
 
-int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int fp64, int adj, Plan *P)
+// i-points per lane of the pair-kernel variant these options select: four
+// for the FP32 n_sigma = 64 kernels without images (registers allow it),
+// two elsewhere.
+int ipl_for(int fp64, int kahan, int nsig, bool img) { return (!fp64 && !kahan && nsig == 64 && !img) ? 4 : 2; }
+
+int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int nsig, int fp64, int adj,
+              Plan *P)
 {
     P->segs.resize(B);
     P->JC = o->j_chunks > 0 ? 1024 * o->j_chunks : 8192;
     const int64_t JC = P->JC;
+    {
+        // the image loop runs when a periodic axis has images or a cut is set
+        int nimg = 1;
+        for (int a = 0; a < 3; ++a)
+            if (grids[0].periodic[a] && o->image_max[a] > 0) nimg *= 2 * o->image_max[a] + 1;
+        const bool img = nimg > 1 || o->r_cut > 0.0;
+        P->BI = ipl_for(fp64, o->kahan, nsig, img) * kPairThreads;
+    }
+    const int64_t BI = P->BI;
     int64_t t_off = 0, slots = 0, rows = 0, fin = 0, Gtot = 0;
     for (int b = 0; b < B; ++b) {
         GridDev g;
@@ -1185,9 +1215,9 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         s.t_off = t_off;
         t_off += s.T;
         // work items if every point were kept (an upper bound for any density)
-        int64_t nib = (g.G + kBI - 1) / kBI, items = 0;
+        int64_t nib = (g.G + BI - 1) / BI, items = 0;
         for (int64_t I = 0; I < nib; ++I) {
-            int64_t rest = g.G - (I + 1) * kBI;
+            int64_t rest = g.G - (I + 1) * BI;
             items += 1 + (rest > 0 ? (rest + JC - 1) / JC : 0);
         }
         s.row_base = rows;
@@ -1249,7 +1279,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     L.gidx = off;
     off = align256(off + Gtot * sizeof(int32_t));
     L.ipart = off;
-    off = align256(off + (size_t)P->NI * slots * kBI * sizeof(double));
+    off = align256(off + (size_t)P->NI * slots * BI * sizeof(double));
     L.jpart = off;
     off = align256(off + (size_t)P->NJ * slots * JC * esz);
     L.blockE = off;
@@ -1289,12 +1319,16 @@ struct PairPtrs {
     void *jpart;
 };
 
-template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC>
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL>
 int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
-    // the kernel's LDS is static (kLdsBytes); nothing to set up
+    // the work layout was made for this row-block length
+    if (a.BI != IPL * kPairThreads)
+        return fail(VDW_EINVAL, "internal: row blocks of %d points planned for a kernel with %d", a.BI,
+                    IPL * kPairThreads);
+    // the kernel's LDS is static (kLdsBytes); nothing else to set up
     if (attr_only) return VDW_OK;
-    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC>), dim3(grid), dim3(kPairThreads), lds, s, a,
+    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC, IPL>), dim3(grid), dim3(kPairThreads), lds, s, a,
                        (const typename RecOf<R>::T *)p.recs, p.segs, p.hdr, p.counter, (const R *)p.tabg, p.imgs,
                        p.rowoff, p.ipart, (R *)p.jpart);
     VDW_HIP(hipGetLastError());
@@ -1302,17 +1336,18 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 }
 
 // Instantiated variants: FP32C with n_sigma = 64 on cubic or general
-// orthorhombic grids (the fast paths), FP32C for any n_sigma, Kahan-
-// compensated FP32C, and plain FP64; each with and without the adjoint
-// sums and the image loop.
+// orthorhombic grids (the fast paths; four i-points per lane without
+// images), FP32C for any n_sigma, Kahan-compensated FP32C, and plain FP64;
+// each with and without the adjoint sums and the image loop.
 template <typename R, bool KAHAN, int NSIG, bool CUBIC>
 int launch_pair_v(int adj, int img, const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s,
                   bool attr_only)
 {
-    if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only)
-                        : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only);
-    return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only)
-               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC>(a, p, grid, lds, s, attr_only);
+    constexpr int W = (sizeof(R) == 4 && !KAHAN && NSIG == 64) ? 4 : 2;  // IPL without images
+    if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC, 2>(a, p, grid, lds, s, attr_only)
+                        : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, W>(a, p, grid, lds, s, attr_only);
+    return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC, 2>(a, p, grid, lds, s, attr_only)
+               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, W>(a, p, grid, lds, s, attr_only);
 }
 
 int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, const PairArgs &a, const PairPtrs &p,
@@ -1362,7 +1397,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     E->nsig = tp->n_sigma;
     E->self_term = o->self_term;
     E->n_cut = o->n_cut;
-    rc = make_plan(B, grids, grid_off, o, E->fp64, adj, &E->P);
+    rc = make_plan(B, grids, grid_off, o, tp->n_sigma, E->fp64, adj, &E->P);
     if (rc) return rc;
     const Plan &P = E->P;
     if (ws_bytes < P.L.total) return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
@@ -1393,6 +1428,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.S = S;
     pa.K = K;
     pa.JC = P.JC;
+    pa.BI = P.BI;
     pa.csig = sqrt((double)(tp->n_sigma - 1));
     pa.tDmax = (double)(tp->n_D - 1);
     pa.tSclamp = E->fp64 ? nextafter((double)(tp->n_sigma - 1), 0.0)
@@ -1404,7 +1440,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.home = P.home;
     pa.NI = P.NI;
     pa.NJ = P.NJ;
-    pa.istride = P.L.slots * kBI;
+    pa.istride = P.L.slots * P.BI;
     pa.jstride = P.L.slots * (int64_t)P.JC;
     // cubic grids take the exact integer form of the squared distance: its
     // partial sums stay below 12 c^2 for coordinates |c| <= c_max (image
@@ -1472,7 +1508,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)L.nblocks), dim3(kCompactThreads), 0, s, (const Seg *)segs, B,
                        n_d, E.n_cut, counts, flag);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, L.nblocks, segs, B, hdr, rowoff,
-                       (int64_t)P.JC);
+                       (int64_t)P.JC, (int64_t)P.BI);
     ScatterArgs sa;
     sa.segs = segs;
     sa.B = B;
@@ -1516,6 +1552,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.istride = E.pa.istride;
     fa.jstride = E.pa.jstride;
     fa.JC = P.JC;
+    fa.BI = P.BI;
     fa.NI = P.NI;
     fa.NJ = P.NJ;
     fa.img = P.img ? 1 : 0;
@@ -1632,7 +1669,7 @@ extern "C" size_t enl_batched_workspace_size(int32_t B, const vdw_grid *grids, c
 {
     if (B < 1 || !grids || validate_opts(opts) || validate_table(tp)) return 0;
     Plan P;
-    if (make_plan(B, grids, nullptr, opts, opts->precision == VDW_FP64, 1, &P)) return 0;
+    if (make_plan(B, grids, nullptr, opts, tp->n_sigma, opts->precision == VDW_FP64, 1, &P)) return 0;
     return P.L.total;
 }
 
