@@ -1,9 +1,16 @@
 """Benchmark: pair evaluations per second of E_c^nl + v_nl on one MI355X.
 
-One step = compute_q0 + enl_potential (energy and dE/dn fused) on the
-Kr2-like dimer (96^3 grid, h = 0.25 bohr, R = 7 bohr, n_cut = 1e-5,
-2048 x 64 kernel table), inputs resident in HBM.  The table is built once on
-the GPU before timing.  Prints one JSON line.
+Default workload (`--workload kr`): the Kr2-like dimer scan.  Five
+separations R = 6, 7, 8, 10, 14 bohr, each with its two atoms alone
+(E(inf) = E(A) + E(B) on the same grid positions), 15 densities on 96^3
+grids (h = 0.25 bohr, n_cut = 1e-5), 2048 x 64 kernel table.  One step is
+the whole batched evaluation — gradient and q0 of every density,
+compaction, the persistent pair kernel over the shared work list, the
+reductions and the adjoint dE/dn — recorded once into a HIP graph and
+replayed, inputs resident in HBM.  The table is built once on the GPU
+before timing.  Prints one JSON line with the binding curve
+E_nl(R) - E_nl(inf), the FP32C-vs-FP64 comparison on the same step, the
+roofline of the pair kernel and the CPU oracle's rate on a sample.
 
 Roofline: the pair kernel is bound by vector ALU work.  It evaluates each
 unordered pair once for both orders; the algorithmic work of one such
@@ -17,7 +24,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -33,7 +39,7 @@ PEAK_FP32_TFLOPS = 157.3
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {"kr": (5054290.3125 * 2.0 + 6034241.21875) * 1024}
 
 
 def parse():
@@ -41,9 +47,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--R", type=float, default=7.0)
-    p.add_argument("--workload", default="kr", choices=["kr", "slab", "batch", "dimer24"],
-                   help="kr: the Kr2-like dimer (the reported metric); slab, batch, dimer24: the other cases")
+    p.add_argument("--R", type=float, default=7.0, help="separation of the kr1 workload (bohr)")
+    p.add_argument("--workload", default="kr", choices=["kr", "kr1", "slab", "batch", "dimer24"],
+                   help="kr: the Kr2-like dimer scan (the reported metric); kr1: one dimer at --R; slab, batch, "
+                        "dimer24: the other cases")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0, help="oracle rows in the CPU sample (0: auto)")
@@ -52,11 +59,38 @@ def parse():
     p.add_argument("--j-chunks", type=int, default=0)
     p.add_argument("--grid-blocks", type=int, default=0)
     p.add_argument("--no-graph", action="store_true",
-                   help="batch workload: call enl_potential_batched per step instead of replaying a recorded graph")
+                   help="batched workloads: call enl_potential_batched per step instead of replaying a recorded graph")
     p.add_argument("--autotune", action="store_true", help="pick j_chunks with the autotuner before timing")
     p.add_argument("--copy-calib", type=int, default=0,
                    help="MiB: run one plain device-to-device copy of this size first (profiler calibration)")
     return p.parse_args()
+
+
+def workloads(a, W):
+    """(densities, description) of the chosen workload."""
+    if a.workload == "kr":
+        wls = []
+        for R in W.KR_SEPARATIONS:
+            wls += [W.kr_dimer(R), W.kr_dimer(R, which="A"), W.kr_dimer(R, which="B")]
+        desc = ("Kr2-like dimer scan: R in {6,7,8,10,14} bohr, each with its two atoms alone (E(inf) = E(A)+E(B)); "
+                "15 densities on 96^3 grids h=0.25 bohr, n_cut=1e-5, table 2048x64 on D<=48; one batched evaluation "
+                "(q0 included, E + dE/dn fused) replayed as a HIP graph")
+    elif a.workload == "kr1":
+        wls = [W.kr_dimer(a.R)]
+        desc = (f"Kr2-like dimer, 96^3 grid h=0.25 bohr, R={a.R:g} bohr, n_cut=1e-5, "
+                f"table 2048x64 on D<=48, energy + potential fused")
+    elif a.workload == "slab":
+        wls = [W.xe_slab()]
+        desc = ("Xe-like slab, 48x48x224 grid of an 8.6x8.6x40 bohr cell, periodic x,y, images |m|,|p|<=3, "
+                "r<=30 bohr, n_cut=1e-5, table 2048x64, energy + potential fused")
+    elif a.workload == "batch":
+        wls = W.molecule_batch(64)
+        desc = ("64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched "
+                "evaluation (q0 included) replayed as a HIP graph")
+    else:
+        wls = [W.dimer_small()]
+        desc = "dimer 24^3 grid h=0.5 bohr, n_cut=1e-6, table 1024x32, energy only"
+    return wls, desc
 
 
 def main():
@@ -78,21 +112,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if a.workload == "kr":
-        wls = [W.kr_dimer(a.R)]
-        desc = (f"Kr2-like dimer, 96^3 grid h=0.25 bohr, R={a.R:g} bohr, n_cut=1e-5, "
-                f"table 2048x64 on D<=48, energy + potential fused")
-    elif a.workload == "slab":
-        wls = [W.xe_slab()]
-        desc = ("Xe-like slab, 48x48x224 grid of an 8.6x8.6x40 bohr cell, periodic x,y, images |m|,|p|<=3, "
-                "r<=30 bohr, n_cut=1e-5, table 2048x64, energy + potential fused")
-    elif a.workload == "batch":
-        wls = W.molecule_batch(64)
-        desc = ("64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched "
-                "evaluation (q0 included) replayed as a HIP graph")
-    else:
-        wls = [W.dimer_small()]
-        desc = "dimer 24^3 grid h=0.5 bohr, n_cut=1e-6, table 1024x32, energy only"
+    print(f"# building the {a.workload} densities", file=sys.stderr, flush=True)
+    wls, desc = workloads(a, W)
     wl = wls[0]
     tparams = V.TableParams(n_D=1024, n_sigma=32, D_max=48.0) if a.workload == "dimer24" else \
         V.TableParams(n_D=2048, n_sigma=64, D_max=48.0)
@@ -104,25 +125,28 @@ def main():
     grids = [V.Grid(w.n, w.h, w.periodic) for w in wls]
     ns = [torch.tensor(w.rho.reshape(-1), dtype=torch.float64, device=dev) for w in wls]
     n, offs = V.pack_batch(grids, ns)
+    del ns
     g = grids[0]
+    batched = len(wls) > 1
 
     def opts(prec):
         return V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec, kahan=a.kahan,
                       table_lds_rows=a.lds_rows, j_chunks=a.j_chunks, grid_blocks=a.grid_blocks)
 
-    graph = a.workload == "batch" and not a.no_graph
+    graph = batched and not a.no_graph
     plans = {}
 
     def eager(prec):
-        if a.workload == "batch":
+        """[(E_pair0, E_pairL, E_self)] per density and dE/dn (packed)."""
+        if batched:
             qd = V.compute_q0_batched(grids, n, offs, wl.n_cut)
-            E, v = V.enl_potential_batched(grids, n, offs, qd, table, opts(prec))
-            return tuple(sum(e[k] for e in E) for k in range(3)), v
+            return V.enl_potential_batched(grids, n, offs, qd, table, opts(prec))
         if a.workload == "dimer24":
             qd = V.compute_q0(g, n, wl.n_cut, derivatives=False)
-            return V.enl_energy(g, n, qd["q0"], table, opts(prec)), n
+            return [V.enl_energy(g, n, qd["q0"], table, opts(prec))], n
         qd = V.compute_q0(g, n, wl.n_cut)
-        return V.enl_potential(g, n, qd, table, opts(prec))
+        E, v = V.enl_potential(g, n, qd, table, opts(prec))
+        return [E], v
 
     def step(prec):
         if not graph:
@@ -136,12 +160,11 @@ def main():
         p.replay()
         return p, None
 
-    def result(prec, out):
+    def result(out):
         if not graph:
             return out
         p = out[0]
-        E = p.energies()
-        return tuple(sum(e[k] for e in E) for k in range(3)), p.dEdn
+        return p.energies(), p.dEdn
 
     def timed(prec, steps, warmup):
         V.set_timing(False)
@@ -159,7 +182,7 @@ def main():
                 kms.append(V.last_stats()["pair_kernel_ms"])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        E, v = result(prec, out)
+        E, v = result(out)
         if graph:
             # pair-kernel time from HIP events around the same kernel in one
             # eager evaluation (a replayed graph carries no events)
@@ -200,6 +223,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": desc,
+            "densities": len(wls),
             "retained_points": st["retained"],
             "pairs_per_step": pairs,
             "lds_rows": st["lds_rows"],
@@ -217,35 +241,46 @@ def main():
         "peak": PEAK_FP32_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_TFLOPS,
-        "traffic": TRAFFIC_BYTES.get(a.workload) if a.R == 7.0 else None,
+        "traffic": TRAFFIC_BYTES.get(a.workload) if a.workload != "kr1" or a.R == 7.0 else None,
         "kernel": "pair_kernel<%s, %s, %s>" % ("double" if a.workload == "dimer24" else "float",
                                                 "energy" if a.workload == "dimer24" else "ADJ",
                                                 "IMG" if a.workload == "slab" else "noIMG"),
         "kernel_ms": kms32,
         "flop_per_unordered_pair": fpp,
     }
-    out["energy_ha"] = {"E_pair0": E32[0], "E_pairL": E32[1], "E_self": E32[2], "E": sum(E32)}
+    tot = [sum(e[k] for e in E32) for k in range(3)]
+    out["energy_ha"] = {"E_pair0": tot[0], "E_pairL": tot[1], "E_self": tot[2], "E": sum(tot)}
+    if a.workload == "kr":
+        scan = []
+        for t, R in enumerate(W.KR_SEPARATIONS):
+            e_ab, e_a, e_b = (sum(E32[3 * t + k]) for k in range(3))
+            scan.append({"R_bohr": R, "E_nl": e_ab, "E_nl_minus_E_inf": e_ab - e_a - e_b})
+        out["scan"] = scan
     out["table_build_s"] = t_table
     if not a.no_fp64 and a.workload != "dimer24":
         steps64 = max(1, a.steps // 2)
         dt64, E64, v64, kms64, _ = timed(V.VDW_FP64, steps64, 1)
         rate64 = pairs * steps64 / dt64
-        dE = abs(sum(E32) - sum(E64)) / abs(sum(E64))
+        dE = max(abs(sum(e32) - sum(e64)) / abs(sum(e64)) for e32, e64 in zip(E32, E64))
         dv = float(torch.linalg.norm(v32 - v64) / torch.linalg.norm(v64))
         out["fp64"] = {"value": rate64, "ms_per_step": 1e3 * dt64 / steps64, "kernel_ms": kms64,
                        "speedup_fp32c_over_fp64": value / rate64,
-                       "fp32c_vs_fp64": {"dE_rel": dE, "dv_rel_l2": dv}}
-    if not a.no_cpu_baseline and a.workload == "kr":
-        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_rows)
+                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dv_rel_l2": dv}}
+        if a.workload == "kr":
+            for t, s in enumerate(out["scan"]):
+                e_ab, e_a, e_b = (sum(E64[3 * t + k]) for k in range(3))
+                s["E_nl_minus_E_inf_fp64"] = e_ab - e_a - e_b
+    if not a.no_cpu_baseline and a.workload in ("kr", "kr1"):
+        out["cpu_baseline"] = cpu_baseline(W.kr_dimer(7.0) if a.workload == "kr" else wl, a.cpu_rows)
     print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(wl, rows):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
-    q0 on the whole grid, then the double-sum rows of a fixed random subset of
-    the kept points against all kept points (energy + adjoint sums).  The
-    oracle table (2048 x 64, a coarser quadrature rule: its values do not
-    change the work per pair) is built before the clock starts."""
+    q0 on the whole grid of one dimer, then the double-sum rows of a fixed
+    random subset of the kept points against all kept points (energy +
+    adjoint sums).  The oracle table (2048 x 64, a coarser quadrature rule: its
+    values do not change the work per pair) is built before the clock starts."""
     import numpy as np
 
     from oracle import oracle as O
@@ -260,7 +295,7 @@ def cpu_baseline(wl, rows):
     idx, ix, iy, iz = O._points(g, qd["keep"])
     N = len(idx)
     if rows <= 0:
-        rows = max(64, int(4e8 * threads / N))  # about 10-20 s of oracle work
+        rows = max(64, int(1e9 * threads / N))  # about 15-20 s of oracle work
     rng = np.random.default_rng(0)
     sel = np.sort(rng.choice(N, size=min(rows, N), replace=False)).astype(np.int64)
     r = wl.rho.reshape(-1)
@@ -269,7 +304,7 @@ def cpu_baseline(wl, rows):
     dt = time.perf_counter() - t0
     pairs = float(len(sel)) * (N - 1)
     return {"value": pairs / dt, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"q0 on all {g.G} grid points + {len(sel)} of {N} rows of the double sum "
+            "sample": f"{wl.name}: q0 on all {g.G} grid points + {len(sel)} of {N} rows of the double sum "
                       f"(E and dE/dq row sums, FP64, OpenMP), {dt:.1f} s"}
 
 
