@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--no-graph", action="store_true",
                    help="batched workloads: call enl_potential_batched per step instead of replaying a recorded graph")
     p.add_argument("--autotune", action="store_true", help="pick j_chunks with the autotuner before timing")
+    p.add_argument("--cpu-only", action="store_true",
+                   help="print the CPU oracle's rate on the sample as JSON and exit (no GPU use)")
     p.add_argument("--copy-calib", type=int, default=0,
                    help="MiB: run one plain device-to-device copy of this size first (profiler calibration)")
     return p.parse_args()
@@ -93,12 +95,35 @@ def workloads(a, W):
     return wls, desc
 
 
+def one_thread_baseline(rows):
+    """The oracle's rate on one thread: a child process (started before this
+    one touches the GPU) with OMP_NUM_THREADS=1 on a smaller sample."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-only", "--cpu-rows", str(rows)]
+    print("# cpu baseline on one thread (child process)", file=sys.stderr, flush=True)
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        print(r.stderr[-2000:], file=sys.stderr)
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU split is a design "
               "note, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if a.cpu_only:
+        import vdw_workloads as W
+
+        print(json.dumps(cpu_baseline(W.kr_dimer(7.0), a.cpu_rows)), flush=True)
+        return
+    one_thread = None
+    if not a.no_cpu_baseline and a.workload in ("kr", "kr1"):
+        one_thread = one_thread_baseline(400)
     import numpy as np
     import torch
 
@@ -270,8 +295,30 @@ def main():
             for t, s in enumerate(out["scan"]):
                 e_ab, e_a, e_b = (sum(E64[3 * t + k]) for k in range(3))
                 s["E_nl_minus_E_inf_fp64"] = e_ab - e_a - e_b
+    if batched and a.workload != "dimer24":
+        # energy only (no adjoint sums, no dE/dn): the same step as a plan without the potential
+        p = V.BatchPlan(grids, offs, table, opts(main_prec), potential=False)
+        p.capture(n)
+        p.replay()
+        torch.cuda.synchronize()
+        steps_e = max(1, a.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps_e):
+            p.replay()
+        torch.cuda.synchronize()
+        dte = time.perf_counter() - t0
+        Ee = p.energies()
+        out["energy_only"] = {"value": pairs * steps_e / dte, "ms_per_step": 1e3 * dte / steps_e,
+                              "dE_rel_max_vs_fused": max(abs(sum(x) - sum(y)) / abs(sum(y)) for x, y in zip(Ee, E32))}
+        p.close()
     if not a.no_cpu_baseline and a.workload in ("kr", "kr1"):
-        out["cpu_baseline"] = cpu_baseline(W.kr_dimer(7.0) if a.workload == "kr" else wl, a.cpu_rows)
+        cb = cpu_baseline(W.kr_dimer(7.0) if a.workload == "kr" else wl, a.cpu_rows)
+        cb["per_core"] = cb["value"] / cb["cores"]
+        if one_thread is not None:
+            cb["one_thread"] = {"value": one_thread["value"], "sample": one_thread["sample"]}
+        cb["context"] = ("the paper's timing (Sec. 5): 130 000 points in 36 min on one 2.13 GHz Core Duo core, "
+                         "i.e. 7.8e6 ordered pairs/s")
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
