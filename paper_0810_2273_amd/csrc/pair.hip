@@ -1165,8 +1165,10 @@ struct Plan {
 };
 
 // i-points per lane of the pair-kernel variant these options select: four
-// for the FP32 n_sigma = 64 kernels without images (registers allow it),
-// two elsewhere.
+// for the FP32 n_sigma = 64 kernels without images, two elsewhere.  (With
+// images, four points per lane was measured slower on the slab: the wider
+// i box of a wavefront lets fewer tiles skip or run unmasked against the
+// cut, and the per-image set-up spills registers.)
 int ipl_for(int fp64, int kahan, int nsig, bool img) { return (!fp64 && !kahan && nsig == 64 && !img) ? 4 : 2; }
 
 int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int nsig, int fp64, int adj,
@@ -1343,7 +1345,7 @@ template <typename R, bool KAHAN, int NSIG, bool CUBIC>
 int launch_pair_v(int adj, int img, const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s,
                   bool attr_only)
 {
-    constexpr int W = (sizeof(R) == 4 && !KAHAN && NSIG == 64) ? 4 : 2;  // IPL without images
+    constexpr int W = (sizeof(R) == 4 && !KAHAN && NSIG == 64) ? 4 : 2;  // i-points per lane without images
     if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC, 2>(a, p, grid, lds, s, attr_only)
                         : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, W>(a, p, grid, lds, s, attr_only);
     return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC, 2>(a, p, grid, lds, s, attr_only)
