@@ -58,6 +58,8 @@ def parse():
     p.add_argument("--lds-rows", type=int, default=-1)
     p.add_argument("--j-chunks", type=int, default=0)
     p.add_argument("--grid-blocks", type=int, default=0)
+    p.add_argument("--block-threads", type=int, default=0,
+                   help="pair-kernel workgroup: 0/1024 (four i-points per lane) or 512 (eight)")
     p.add_argument("--no-graph", action="store_true",
                    help="batched workloads: call enl_potential_batched per step instead of replaying a recorded graph")
     p.add_argument("--autotune", action="store_true", help="pick j_chunks with the autotuner before timing")
@@ -156,7 +158,8 @@ def main():
 
     def opts(prec):
         return V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec, kahan=a.kahan,
-                      table_lds_rows=a.lds_rows, j_chunks=a.j_chunks, grid_blocks=a.grid_blocks)
+                      table_lds_rows=a.lds_rows, j_chunks=a.j_chunks, grid_blocks=a.grid_blocks,
+                      block_threads=a.block_threads)
 
     graph = batched and not a.no_graph
     plans = {}
@@ -228,8 +231,8 @@ def main():
             grids, n, offs, wl.n_cut), table, o), base, kept=int((n >= wl.n_cut).sum()),
             nimg=int(np.prod([2 * m + 1 if per else 1 for m, per in zip(wl.image_max, wl.periodic)])),
             batch=len(wls), verbose=True)
-        a.j_chunks = tuned.j_chunks
-        print(f"# autotune: j_chunks={a.j_chunks}", file=sys.stderr, flush=True)
+        a.j_chunks, a.block_threads = tuned.j_chunks, tuned.block_threads
+        print(f"# autotune: block_threads={a.block_threads} j_chunks={a.j_chunks}", file=sys.stderr, flush=True)
     dt, E32, v32, kms32, st = timed(main_prec, a.steps, a.warmup)
     pairs = st["pairs"]
     value = pairs * a.steps / dt
@@ -254,6 +257,7 @@ def main():
             "lds_rows": st["lds_rows"],
             "j_chunks": st["j_chunks"],
             "grid_blocks": st["grid_blocks"],
+            "block_threads": st["block_threads"],
             "kahan": a.kahan,
             "hip_graph": graph,
         },

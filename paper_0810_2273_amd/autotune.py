@@ -1,12 +1,14 @@
 """Tile autotuner for the pair kernel.
 
-The free tile parameter is the j-chunk length of the off-diagonal work
+Two tile parameters are free.  The j-chunk length of the off-diagonal work
 items (``Opts.j_chunks`` x 1024 points): short chunks give many small items
 (good load balance, more partial sums to write and reduce), long chunks the
-opposite.  The row block (2048 i-points, two per lane) and the workgroup
-shape (16 wavefronts, one workgroup per CU because the table fills the LDS)
-are fixed by the register and LDS budgets.  ``tune`` times the pair kernel
-(HIP events around the launch, read back through ``last_stats``) for each
+opposite.  The workgroup shape of the FP32 n_sigma = 64 kernels without
+images (``Opts.block_threads``): 1024 threads with four i-points per lane,
+or 512 with eight (fewer instructions per pair, half the wavefronts to hide
+LDS and L2 latency); both keep row blocks of 4096 points, and one workgroup
+per CU because the table fills the LDS.  ``tune`` times the pair kernel (HIP
+events around the launch, read back through ``last_stats``) for each
 candidate and caches the fastest per device and workload class.
 """
 from __future__ import annotations
@@ -22,6 +24,7 @@ import torch
 from . import api
 
 CANDIDATES = (2, 4, 8, 16, 32)
+BLOCK_THREADS = (1024, 512)
 
 
 def _cache_path() -> str:
@@ -60,32 +63,40 @@ def _store(d: dict) -> None:
 
 
 def tune(run, opts: api.Opts, kept: int, nimg: int = 1, potential: bool = True, batch: int = 1,
-         candidates=CANDIDATES, repeats: int = 2, use_cache: bool = True, verbose: bool = False) -> api.Opts:
-    """Pick ``j_chunks`` for ``run(opts)`` (a callable doing one evaluation)
-    by timing the pair kernel; returns a copy of ``opts`` with the choice."""
+         candidates=CANDIDATES, block_threads=BLOCK_THREADS, repeats: int = 2, use_cache: bool = True,
+         verbose: bool = False) -> api.Opts:
+    """Pick ``j_chunks`` and ``block_threads`` for ``run(opts)`` (a callable
+    doing one evaluation) by timing the pair kernel; returns a copy of
+    ``opts`` with the choice.  Workgroup shapes that the options' kernel
+    variant does not have (it reports another size) are skipped."""
     key = _key(kept, nimg, opts.precision, potential, batch)
     cache = _load() if use_cache else {}
     if key in cache:
-        return replace(opts, j_chunks=int(cache[key]["j_chunks"]))
+        c = cache[key]
+        return replace(opts, j_chunks=int(c["j_chunks"]), block_threads=int(c.get("block_threads", 0)))
     best, best_ms, report = None, math.inf, {}
     api.set_timing(True)
     try:
-        for jc in candidates:
-            o = replace(opts, j_chunks=jc)
-            run(o)  # warm
-            ms = []
-            for _ in range(repeats):
-                run(o)
-                ms.append(api.last_stats()["pair_kernel_ms"])
-            t = min(ms)
-            report[jc] = t
-            if verbose:
-                print(f"# autotune j_chunks={jc}: {t:.3f} ms", flush=True)
-            if t < best_ms:
-                best, best_ms = jc, t
+        for bt in block_threads:
+            for jc in candidates:
+                o = replace(opts, j_chunks=jc, block_threads=bt)
+                run(o)  # warm
+                if api.last_stats()["block_threads"] != bt:
+                    break  # this variant has one workgroup shape only
+                ms = []
+                for _ in range(repeats):
+                    run(o)
+                    ms.append(api.last_stats()["pair_kernel_ms"])
+                t = min(ms)
+                report[f"{bt}/{jc}"] = t
+                if verbose:
+                    print(f"# autotune block_threads={bt} j_chunks={jc}: {t:.3f} ms", flush=True)
+                if t < best_ms:
+                    best, best_ms = (bt, jc), t
     finally:
         api.set_timing(False)
-    cache[key] = {"j_chunks": best, "ms": best_ms, "sweep": report, "when": time.time()}
+    cache[key] = {"block_threads": best[0], "j_chunks": best[1], "ms": best_ms, "sweep": report,
+                  "when": time.time()}
     if use_cache:
         _store(cache)
-    return replace(opts, j_chunks=best)
+    return replace(opts, block_threads=best[0], j_chunks=best[1])

@@ -45,18 +45,17 @@ namespace {
 
 constexpr int kCompactBlock = 1024;  // brick-order positions per count/scatter block
 constexpr int kCompactThreads = 256;  // 4 positions (one brick row) per thread
-constexpr int kPairThreads = 1024;    // threads of a pair workgroup
-constexpr int kWaves = kPairThreads / 64;
+constexpr int kPairThreads = 1024;    // threads of a pair workgroup (512 for the eight-point variant)
 constexpr int kFinThreads = 256;      // points per finalize block
 constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 carry (diagonal items)
 constexpr int kLdsBytes = 160 * 1024; // LDS of one gfx950 workgroup
 
-// Table elements a pair workgroup keeps in LDS, next to its j-side
-// reduction buffer (kWaves x NJ x 64) and the work-item slot.
+// Table elements a pair workgroup of NW wavefronts keeps in LDS, next to
+// its j-side reduction buffer (NW x NJ x 64) and the work-item slot.
 template <typename R>
-constexpr int tab_elems(int NJ)
+constexpr int tab_elems(int NJ, int NW)
 {
-    return (int)((kLdsBytes - kWaves * NJ * 64 * sizeof(R) - 64) / sizeof(R));
+    return (int)((kLdsBytes - NW * NJ * 64 * sizeof(R) - 64) / sizeof(R));
 }
 
 enum { HDR_ITEMS = 0, HDR_NTOTAL = 1, HDR_BLKS = 2, HDR_WORDS = 8 };
@@ -311,7 +310,7 @@ struct PairArgs {
     int B;
     int nD, nS, S, K;   // S: LDS row stride (n_sigma + 1); K: rows held in LDS
     int JC;             // j-points per off-diagonal item (multiple of 64)
-    int BI;             // i-points per row block (IPL x kPairThreads of the variant)
+    int BI;             // i-points per row block (IPL x threads of the variant)
     double tDmax;       // n_D - 1: table branch iff t_D = D / dD < n_D - 1
     double tSclamp;     // largest value below n_sigma - 1 (sigma index clamp)
     double csig;        // sqrt(n_sigma - 1)
@@ -650,8 +649,8 @@ __device__ inline void box_dist2(const R *bi, const R *bj, R sx, R sy, R sz, R w
 // Pointers are separate __restrict__ parameters so the compiler knows the
 // records, segments and table are not written during the kernel and can
 // fetch wave-uniform records with scalar loads.
-template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL>
-__global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const typename RecOf<R>::T *__restrict__ recs,
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL, int TPB>
+__global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename RecOf<R>::T *__restrict__ recs,
                                                             const Seg *__restrict__ segs,
                                                             const int64_t *__restrict__ hdr, int *__restrict__ counter,
                                                             const R *__restrict__ tabg, const int *__restrict__ imgs,
@@ -663,8 +662,9 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
     constexpr bool NORM = CUBIC && sizeof(R) == 4;
     // static LDS: the table rows (K x S, row stride S = n_sigma + 1), the
     // j-side sums of one tile from every wavefront, the work-item slot
-    __shared__ __align__(16) R tab[tab_elems<R>(NJc)];
-    __shared__ R red[kWaves * NJc * 64];
+    constexpr int NW = TPB / 64;  // wavefronts of the workgroup
+    __shared__ __align__(16) R tab[tab_elems<R>(NJc, NW)];
+    __shared__ R red[NW * NJc * 64];
     __shared__ int s_item_v;
     int *s_item = &s_item_v;
 
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
     kc.nS = nS;
     kc.K = A.K;
 
-    for (int t = threadIdx.x; t < A.K * nS; t += kPairThreads) {
+    for (int t = threadIdx.x; t < A.K * nS; t += TPB) {
         int r = t / nS, c = t - r * nS;
         tab[r * A.S + c] = tabg[t];
         // column n_sigma: linear continuation of the last cell (FP32 form)
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
 
         // IPL i-points per lane: point p of lane l of wavefront w is number
         // w (64 IPL) + 64 p + l of the row block
-        constexpr int BI = IPL * kPairThreads;
+        constexpr int BI = IPL * TPB;
         bool act[IPL];
         Rec Ir[IPL];
         R ai[IPL], ci[IPL], ni[IPL];
@@ -893,7 +893,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_kernel(PairArgs A, const ty
                 if (threadIdx.x < NJc * 64) {
                     const int a = threadIdx.x >> 6, jl = threadIdx.x & 63;
                     R sum = 0;
-                    for (int v = 0; v < kWaves; ++v) sum += red[(v * NJc + a) * 64 + jl];
+                    for (int v = 0; v < NW; ++v) sum += red[(v * NJc + a) * 64 + jl];
                     if (t0 + jl < J1) jpart[a * A.jstride + slot * A.JC + (t0 + jl - J0)] = sum;
                 }
                 __syncthreads();
@@ -1300,8 +1300,8 @@ int validate_opts(const vdw_opts *o)
     if (!(o->n_cut > 0.0) || !isfinite(o->n_cut)) return fail(VDW_EINVAL, "n_cut must be > 0");
     if (o->precision != VDW_FP64 && o->precision != VDW_FP32C) return fail(VDW_EINVAL, "precision must be 0 or 1");
     if (o->self_term != 0 && o->self_term != 1) return fail(VDW_EINVAL, "self_term must be 0 or 1");
-    if (o->block_threads != 0 && o->block_threads != kPairThreads)
-        return fail(VDW_EINVAL, "block_threads must be 0 or %d", kPairThreads);
+    if (o->block_threads != 0 && o->block_threads != 1024 && o->block_threads != 512)
+        return fail(VDW_EINVAL, "block_threads must be 0, 512 or 1024");
     if (o->j_chunks < 0 || o->j_chunks > 64) return fail(VDW_EINVAL, "j_chunks must be in 0..64");
     if (o->grid_blocks < 0) return fail(VDW_EINVAL, "grid_blocks must be >= 0");
     if (o->kahan != 0 && o->kahan != 1) return fail(VDW_EINVAL, "kahan must be 0 or 1");
@@ -1321,16 +1321,15 @@ struct PairPtrs {
     void *jpart;
 };
 
-template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL>
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL, int TPB>
 int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
     // the work layout was made for this row-block length
-    if (a.BI != IPL * kPairThreads)
-        return fail(VDW_EINVAL, "internal: row blocks of %d points planned for a kernel with %d", a.BI,
-                    IPL * kPairThreads);
+    if (a.BI != IPL * TPB)
+        return fail(VDW_EINVAL, "internal: row blocks of %d points planned for a kernel with %d", a.BI, IPL * TPB);
     // the kernel's LDS is static (kLdsBytes); nothing else to set up
     if (attr_only) return VDW_OK;
-    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC, IPL>), dim3(grid), dim3(kPairThreads), lds, s, a,
+    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC, IPL, TPB>), dim3(grid), dim3(TPB), lds, s, a,
                        (const typename RecOf<R>::T *)p.recs, p.segs, p.hdr, p.counter, (const R *)p.tabg, p.imgs,
                        p.rowoff, p.ipart, (R *)p.jpart);
     VDW_HIP(hipGetLastError());
@@ -1338,28 +1337,34 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 }
 
 // Instantiated variants: FP32C with n_sigma = 64 on cubic or general
-// orthorhombic grids (the fast paths; four i-points per lane without
-// images), FP32C for any n_sigma, Kahan-compensated FP32C, and plain FP64;
-// each with and without the adjoint sums and the image loop.
+// orthorhombic grids (the fast paths: without images four i-points per lane
+// in 1024-thread workgroups, or eight in 512-thread ones), FP32C for any
+// n_sigma, Kahan-compensated FP32C, and plain FP64 (two per lane, 1024
+// threads); each with and without the adjoint sums and the image loop.
 template <typename R, bool KAHAN, int NSIG, bool CUBIC>
-int launch_pair_v(int adj, int img, const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s,
-                  bool attr_only)
+int launch_pair_v(int adj, int img, int tpb, const PairArgs &a, const PairPtrs &p, int grid, size_t lds,
+                  hipStream_t s, bool attr_only)
 {
-    constexpr int W = (sizeof(R) == 4 && !KAHAN && NSIG == 64) ? 4 : 2;  // i-points per lane without images
-    if (adj) return img ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC, 2>(a, p, grid, lds, s, attr_only)
-                        : launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, W>(a, p, grid, lds, s, attr_only);
-    return img ? launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC, 2>(a, p, grid, lds, s, attr_only)
-               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, W>(a, p, grid, lds, s, attr_only);
+    constexpr bool FAST = sizeof(R) == 4 && !KAHAN && NSIG == 64;
+    if (img) return adj ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC, 2, 1024>(a, p, grid, lds, s, attr_only)
+                        : launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC, 2, 1024>(a, p, grid, lds, s, attr_only);
+    if (FAST && tpb == 512)
+        return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only)
+                   : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only);
+    constexpr int W = FAST ? 4 : 2;
+    return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, W, 1024>(a, p, grid, lds, s, attr_only)
+               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, W, 1024>(a, p, grid, lds, s, attr_only);
 }
 
-int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, const PairArgs &a, const PairPtrs &p,
-                int grid, size_t lds, hipStream_t s, bool attr_only)
+int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, int tpb, const PairArgs &a,
+                const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
-    if (fp64) return launch_pair_v<double, false, 0, false>(adj, img, a, p, grid, lds, s, attr_only);
-    if (kahan) return launch_pair_v<float, true, 0, false>(adj, img, a, p, grid, lds, s, attr_only);
-    if (nsig == 64) return cubic ? launch_pair_v<float, false, 64, true>(adj, img, a, p, grid, lds, s, attr_only)
-                                 : launch_pair_v<float, false, 64, false>(adj, img, a, p, grid, lds, s, attr_only);
-    return launch_pair_v<float, false, 0, false>(adj, img, a, p, grid, lds, s, attr_only);
+    if (fp64) return launch_pair_v<double, false, 0, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (kahan) return launch_pair_v<float, true, 0, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (nsig == 64)
+        return cubic ? launch_pair_v<float, false, 64, true>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                     : launch_pair_v<float, false, 64, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    return launch_pair_v<float, false, 0, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
 }
 
 // Everything an evaluation needs that does not depend on the data: the
@@ -1367,6 +1372,7 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, cons
 struct Exec {
     Plan P;
     int B = 0, adj = 0, fp64 = 0, kahan = 0, nsig = 0, cubic = 1, self_term = 0;
+    int tpb = 1024;  // pair-kernel workgroup size
     int K = 0, grid = 0;
     size_t lds = 0;
     double n_cut = 0.0, dD = 0.0, Dmax = 0.0, casym = 0.0;
@@ -1409,7 +1415,10 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
         return fail(VDW_EUNSUPPORTED, "the pair kernel needs %d bytes of LDS per workgroup (device: %zu)", kLdsBytes,
                     dev.lds_per_block);
     // table rows that fit in the kernel's static LDS next to its reduction buffer
-    const int cap = E->fp64 ? tab_elems<double>(P.NJ) : tab_elems<float>(P.NJ);
+    // 512-thread workgroups (eight i-points per lane) on request for the FP32
+    // n_sigma = 64 kernels without images; 1024 everywhere else
+    E->tpb = (!E->fp64 && !E->kahan && tp->n_sigma == 64 && !P.img && o->block_threads == 512) ? 512 : 1024;
+    const int cap = E->fp64 ? tab_elems<double>(P.NJ, E->tpb / 64) : tab_elems<float>(P.NJ, E->tpb / 64);
     int K = cap / S;
     if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
     if (K > tp->n_D) K = tp->n_D;
@@ -1457,7 +1466,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     }
     if (12.0 * cmax * cmax >= 16777216.0) E->cubic = 0;
     PairPtrs none{};
-    return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->cubic, pa, none, E->grid, E->lds, nullptr,
+    return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->cubic, E->tpb, pa, none, E->grid, E->lds, nullptr,
                        true);
 }
 
@@ -1538,7 +1547,8 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     pp.ipart = ipart;
     pp.jpart = jpart;
     if (ev0) VDW_HIP(hipEventRecord(ev0, s));
-    int rc = launch_pair(E.fp64, E.adj, P.img ? 1 : 0, E.kahan, E.nsig, E.cubic, E.pa, pp, E.grid, E.lds, s, false);
+    int rc = launch_pair(E.fp64, E.adj, P.img ? 1 : 0, E.kahan, E.nsig, E.cubic, E.tpb, E.pa, pp, E.grid, E.lds, s,
+                         false);
     if (rc) return rc;
     if (ev1) VDW_HIP(hipEventRecord(ev1, s));
 
@@ -1609,7 +1619,7 @@ void set_stats(const Exec &E, const double *host, float ms)
     g_stats.pairs = pairs;
     g_stats.pair_kernel_ms = ms;
     g_stats.lds_rows = E.K;
-    g_stats.block_threads = kPairThreads;
+    g_stats.block_threads = E.tpb;
     g_stats.j_chunks = E.P.JC / 1024;
     g_stats.grid_blocks = E.grid;
 }

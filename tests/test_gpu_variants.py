@@ -2,7 +2,8 @@
 size or not at all, element by element against the oracle (energies 1e-12 /
 1e-6, dE/dn 1e-10 / 1e-4 in the L2 norm for the FP64 / FP32C forms):
 
-* four i-points per lane on a non-cubic grid (difference form of r^2);
+* four i-points per lane on a non-cubic grid (difference form of r^2), and
+  eight per lane in 512-thread workgroups on cubic and non-cubic grids;
 * the Kahan-compensated FP32 variant;
 * a cubic periodic grid whose image-shifted coordinates are too large for
   the exact integer form of r^2 (|x_i|^2 + |x_j|^2 alone passes 2^24 for
@@ -79,6 +80,23 @@ def test_non_cubic_grid_four_points_per_lane(V, oracle, big, prec):
     wl = W.random_small(n=(34, 30, 28), h=(0.40, 0.45, 0.35), seed=21, n_cut=1e-3)
     st = _run_check(V, oracle, wl, tp, tab, prec, "non-cubic")
     assert st["retained"] > 4 * 4096 and st["retained"] % 4096 != 0
+
+
+@pytest.mark.parametrize("cubic", [True, False])
+def test_eight_points_per_lane(V, oracle, big, cubic):
+    """block_threads = 512: eight i-points per lane, same row blocks of 4096,
+    on a cubic 30^3 dimer (with the LDS rows cut to 40 so the global-table
+    pass runs too) and on the non-cubic grid above."""
+    tp, tab = big
+    if cubic:
+        wl = W.scaled_dimer(edge=30, h=0.4, R=5.0)
+        for rows in (-1, 40):
+            st = _run_check(V, oracle, wl, tp, tab, "fp32c", f"eight-point cubic rows={rows}", block_threads=512,
+                            table_lds_rows=rows)
+    else:
+        wl = W.random_small(n=(34, 30, 28), h=(0.40, 0.45, 0.35), seed=21, n_cut=1e-3)
+        st = _run_check(V, oracle, wl, tp, tab, "fp32c", "eight-point non-cubic", block_threads=512)
+    assert st["block_threads"] == 512
 
 
 def test_kahan_variant(V, oracle, big):
