@@ -12,20 +12,22 @@
 //   scatter   compact the kept points into 32-byte (FP32) or 64-byte (FP64)
 //             records in brick order (4x4x4 bricks, so a wavefront's
 //             i-points are spatially compact and their table rows coherent)
-//   pair      persistent workgroups pull work items from an atomic counter.
-//             The kept points of a density are cut into row blocks of 2048
-//             (two i-points per lane).  Row block I owns one diagonal item
-//             (ordered pairs inside the block, j records streamed through
-//             scalar registers) and items (I, c) pairing it with chunks of
-//             the points after the block.  Off-diagonal pairs are evaluated
-//             once for both orders: each wavefront loads a 64-record j tile
-//             into its lanes and rotates it one lane per step (DPP wave
-//             rotate), carrying the j-side sums with the records, so after
-//             64 steps every lane has met every j and every j-side sum is
-//             back in its home lane; the 16 wavefronts then add their
-//             j-side sums in a fixed order through LDS.  The first table
-//             rows sit in LDS (row stride n_sigma + 1), the rest is read
-//             through L2.
+//   pair      persistent workgroups (one per CU) pull work items from an
+//             atomic counter.  The kept points of a density are cut into
+//             row blocks of IPL x (workgroup size) points, IPL i-points per
+//             lane (four for the FP32 n_sigma = 64 kernels without images,
+//             two elsewhere).  Row block I owns one diagonal item (ordered
+//             pairs inside the block, j records streamed through scalar
+//             registers) and items (I, c) pairing it with chunks of the
+//             points after the block.  Off-diagonal pairs are evaluated once
+//             for both orders: each wavefront loads a 64-record j tile into
+//             its lanes and rotates it one lane per step (DPP wave rotate),
+//             carrying the j-side sums with the records, so after 64 steps
+//             every lane has met every j and every j-side sum is back in its
+//             home lane; the wavefronts then add their j-side sums in a fixed
+//             order through LDS.  The first table rows sit in static LDS
+//             (row stride n_sigma + 1), the rest is read through L2 in a
+//             second pass taken only by the pairs beyond them.
 //   finalize  per point: fixed-order sum of its item partials, on-site term,
 //             energy terms, and (potential) the direct part of dE/dn
 //   reduce    per density: fixed-order sum of the block partials
