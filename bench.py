@@ -39,7 +39,7 @@ PEAK_FP32_TFLOPS = 157.3
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
-TRAFFIC_BYTES = {"kr": (5054290.3125 * 2.0 + 6034241.21875) * 1024}
+TRAFFIC_BYTES = {"kr": (5049320.125 * 2.0 + 6034241.21875) * 1024}
 
 
 def parse():

@@ -97,7 +97,9 @@ typedef struct {
                                compensated FP32 runs carried in FP64)             */
     int32_t self_term;      /* 1: add the on-site term E_self (below); 0: omit     */
     int32_t table_lds_rows; /* rows of the table kept in LDS; -1: as many as fit  */
-    int32_t block_threads;  /* pair-kernel workgroup size: 0 or 1024 (fixed)      */
+    int32_t block_threads;  /* pair-kernel workgroup size: 0 or 1024 (four
+                               i-points per lane), or 512 (eight per lane; FP32C
+                               with n_sigma = 64 and no images, else 1024)       */
     int32_t j_chunks;       /* j-points per off-diagonal work item, in units of
                                1024 (1..64); 0: auto (8)                          */
     int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
