@@ -629,6 +629,21 @@ __device__ inline R wave_max(R v)
     return v;
 }
 
+// A wavefront-uniform copy of lane 0's value.  The builtin moves 32-bit
+// integers, so floating-point values travel as their bit patterns (a plain
+// call would convert them to int and truncate).
+__device__ inline float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ inline double uniform(double v)
+{
+    int2 b = __builtin_bit_cast(int2, v);
+    b.x = __builtin_amdgcn_readfirstlane(b.x);
+    b.y = __builtin_amdgcn_readfirstlane(b.y);
+    return __builtin_bit_cast(double, b);
+}
+
 // Smallest and largest squared distance (units of h_x^2) between two boxes
 // whose x, y, z ranges are given, after shifting the second by (sx, sy, sz).
 template <typename R>
@@ -825,8 +840,8 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                     hi[2] = max(hi[2], Ir[p].z);
                 }
                 for (int a3 = 0; a3 < 3; ++a3) {
-                    ib[2 * a3] = __builtin_amdgcn_readfirstlane(wave_min<R>(lo[a3]));
-                    ib[2 * a3 + 1] = __builtin_amdgcn_readfirstlane(wave_max<R>(hi[a3]));
+                    ib[2 * a3] = uniform(wave_min<R>(lo[a3]));
+                    ib[2 * a3 + 1] = uniform(wave_max<R>(hi[a3]));
                 }
             }
             for (int t0 = J0; t0 < J1; t0 += 64) {
@@ -835,12 +850,12 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 const Rec Jr = P[jv ? jj : J1 - 1];
                 R jb6[6] = {0, 0, 0, 0, 0, 0};
                 if (prune) {
-                    jb6[0] = __builtin_amdgcn_readfirstlane(wave_min<R>(Jr.x));
-                    jb6[1] = __builtin_amdgcn_readfirstlane(wave_max<R>(Jr.x));
-                    jb6[2] = __builtin_amdgcn_readfirstlane(wave_min<R>(Jr.y));
-                    jb6[3] = __builtin_amdgcn_readfirstlane(wave_max<R>(Jr.y));
-                    jb6[4] = __builtin_amdgcn_readfirstlane(wave_min<R>(Jr.z));
-                    jb6[5] = __builtin_amdgcn_readfirstlane(wave_max<R>(Jr.z));
+                    jb6[0] = uniform(wave_min<R>(Jr.x));
+                    jb6[1] = uniform(wave_max<R>(Jr.x));
+                    jb6[2] = uniform(wave_min<R>(Jr.y));
+                    jb6[3] = uniform(wave_max<R>(Jr.y));
+                    jb6[4] = uniform(wave_min<R>(Jr.z));
+                    jb6[5] = uniform(wave_max<R>(Jr.z));
                 }
                 R jSc = 0, jSL = 0, jSq = 0;
                 for (int L = 0; L < nimg; ++L) {

@@ -208,16 +208,18 @@ def test_multi_tile_dimer_parity(V, dev, oracle, big_table, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32c"])
 def test_slab_images_parity(V, dev, oracle, big_table, prec):
     """The Xe-slab shape on a coarse 12 x 12 x 40 grid, images |m|, |p| <= 3 and
-    the 30 bohr cut."""
+    the 30 bohr cut; with all LDS rows and with 40 (then most pairs take the
+    global-table pass)."""
     tp, tab = big_table
     wl = W.scaled_slab(nxy=12, nz=40)
     p, etol, vtol = FP[prec]
-    say(f"slab 12x12x40 {prec}")
     ref = oracle.evaluate(oracle.Grid(wl.n, wl.h, wl.periodic), wl.rho, tab, tp, wl.n_cut, wl.image_max, wl.r_cut,
                           potential=True)
-    E, v = _run(V, dev, wl, _gpu_table(V, dev, tp, tab), p)
-    _check(E, v, ref, etol, vtol, "slab")
-    assert abs(E[1]) > 0
+    for rows in (-1, 40):
+        say(f"slab 12x12x40 {prec} lds_rows={rows}")
+        E, v = _run(V, dev, wl, _gpu_table(V, dev, tp, tab), p, table_lds_rows=rows)
+        _check(E, v, ref, etol, vtol, f"slab rows={rows}")
+        assert abs(E[1]) > 0
 
 
 def test_edge_cases(V, dev, oracle, small_table):
