@@ -36,6 +36,14 @@ if ROOT not in sys.path:
 FLOP_PER_UNORDERED_PAIR = 45
 FLOP_PER_UNORDERED_PAIR_ENERGY = 30
 PEAK_FP32_TFLOPS = 157.3
+# Counter figures of the same kernel and workload from the rocprofv3 runs in
+# profiles/ (executed FP32 FLOP from SQ_INSTS_VALU_FLOPS_FP32 x 64, VALU
+# instructions against wave64 issue slots from GRBM_GUI_ACTIVE); reported
+# beside the live roofline, not measured by this script.
+PROFILE_COUNTERS = {
+    "kr": {"source": "profiles/pair_kernel_kr_scan96_fp32c.md", "executed_tflops": 47.3, "executed_frac": 0.301,
+           "valu_instructions_per_issue_slot": 1.11, "lane_instructions_per_unordered_pair": 39.9},
+}
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
@@ -277,6 +285,8 @@ def main():
         "kernel_ms": kms32,
         "flop_per_unordered_pair": fpp,
     }
+    if a.workload in PROFILE_COUNTERS:
+        out["roofline"]["counters"] = PROFILE_COUNTERS[a.workload]
     tot = [sum(e[k] for e in E32) for k in range(3)]
     out["energy_ha"] = {"E_pair0": tot[0], "E_pairL": tot[1], "E_self": tot[2], "E": sum(tot)}
     if a.workload == "kr":
