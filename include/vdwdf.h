@@ -97,11 +97,21 @@ typedef struct {
                                compensated FP32 runs carried in FP64)             */
     int32_t self_term;      /* 1: add the on-site term E_self (below); 0: omit     */
     int32_t table_lds_rows; /* rows of the table kept in LDS; -1: as many as fit  */
-    int32_t block_threads;  /* pair-kernel workgroup size: 0 or 1024 (four
-                               i-points per lane), or 512 (eight per lane; FP32C
-                               with n_sigma = 64 and no images, else 1024)       */
+    int32_t block_threads;  /* pair-kernel workgroup size: 1024 (row blocks of
+                               4096 points for FP32C with n_sigma = 64 and no
+                               images, else 2048); 512 (eight i-points per
+                               lane, the same blocks; FP32C with n_sigma = 64
+                               and no images, else 1024); 256 (blocks of 512;
+                               no images, else 1024); 0: auto (256 when, with
+                               every grid point kept, the 1024-thread work
+                               list at 1024-point chunks has fewer than 128
+                               items and there are no images; else 1024)     */
     int32_t j_chunks;       /* j-points per off-diagonal work item, in units of
-                               1024 (1..64); 0: auto (8)                          */
+                               1024 (1..64); 0: auto (the longest of 8, 4, 2,
+                               1 whose work list, with every grid point kept,
+                               has at least 4096 items; else 1).  Chunks
+                               shorter than a row block split its diagonal
+                               work into (block / chunk) items.               */
     int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
     int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only)     */
 } vdw_opts;
@@ -277,6 +287,7 @@ typedef struct {
     int32_t block_threads;
     int32_t j_chunks;
     int32_t grid_blocks;
+    int32_t diag_items;     /* diagonal work items per row block */
 } vdw_stats;
 
 int vdw_last_stats(vdw_stats *out);

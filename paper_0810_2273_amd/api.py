@@ -321,7 +321,8 @@ def last_stats() -> dict:
     s = L.VdwStats()
     L.check(L.lib().vdw_last_stats(ct.byref(s)))
     return dict(retained=s.retained, pairs=s.pairs, pair_kernel_ms=s.pair_kernel_ms, lds_rows=s.lds_rows,
-                block_threads=s.block_threads, j_chunks=s.j_chunks, grid_blocks=s.grid_blocks)
+                block_threads=s.block_threads, j_chunks=s.j_chunks, grid_blocks=s.grid_blocks,
+                diag_items=s.diag_items)
 
 
 def set_timing(on: bool):

@@ -3,13 +3,17 @@
 Two tile parameters are free.  The j-chunk length of the off-diagonal work
 items (``Opts.j_chunks`` x 1024 points): short chunks give many small items
 (good load balance, more partial sums to write and reduce), long chunks the
-opposite.  The workgroup shape of the FP32 n_sigma = 64 kernels without
-images (``Opts.block_threads``): 1024 threads with four i-points per lane,
-or 512 with eight (fewer instructions per pair, half the wavefronts to hide
-LDS and L2 latency); both keep row blocks of 4096 points, and one workgroup
-per CU because the table fills the LDS.  ``tune`` times the pair kernel (HIP
-events around the launch, read back through ``last_stats``) for each
-candidate and caches the fastest per device and workload class.
+opposite; chunks shorter than a row block also split its diagonal work.
+The workgroup shape (``Opts.block_threads``): 1024 threads (row blocks of
+4096 points for the FP32 n_sigma = 64 kernels, 2048 otherwise); 512 with
+eight i-points per lane for the FP32 n_sigma = 64 kernels without images
+(fewer instructions per pair, half the wavefronts to hide LDS and L2
+latency); 256 with row blocks of 512 points for any kernel without images
+(more, smaller items for densities too small to fill the chip).  There is
+one workgroup per CU in every shape because the table fills the LDS.
+``tune`` times the pair kernel (HIP events around the launch, read back
+through ``last_stats``) for each candidate and caches the fastest per device
+and workload class.
 """
 from __future__ import annotations
 
@@ -24,7 +28,7 @@ import torch
 from . import api
 
 CANDIDATES = (2, 4, 8, 16, 32)
-BLOCK_THREADS = (1024, 512)
+BLOCK_THREADS = (1024, 512, 256)
 
 
 def _cache_path() -> str:

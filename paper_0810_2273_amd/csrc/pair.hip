@@ -47,7 +47,7 @@ namespace {
 
 constexpr int kCompactBlock = 1024;  // brick-order positions per count/scatter block
 constexpr int kCompactThreads = 256;  // 4 positions (one brick row) per thread
-constexpr int kPairThreads = 1024;    // threads of a pair workgroup (512 for the eight-point variant)
+constexpr int kPairThreads = 1024;    // default pair workgroup size (variants: 512 and 256)
 constexpr int kFinThreads = 256;      // points per finalize block
 constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 carry (diagonal items)
 constexpr int kLdsBytes = 160 * 1024; // LDS of one gfx950 workgroup
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kCompactThreads) void count_kernel(const Seg *__res
 // total appended), then the per-density offsets the later kernels use.
 __global__ __launch_bounds__(1024) void scan_kernel(int64_t *__restrict__ counts, int64_t nblocks,
                                                     Seg *__restrict__ segs, int B, int64_t *__restrict__ hdr,
-                                                    int64_t *__restrict__ rowoff, int64_t JC, int64_t BI)
+                                                    int64_t *__restrict__ rowoff, int64_t JC, int64_t BI, int64_t ND)
 {
     __shared__ int64_t part[1024];
     const int t = threadIdx.x;
@@ -204,12 +204,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t *__restrict__ counts
             g.p_off = counts[first];
             g.N = counts[last] - counts[first];
             g.nIB = (g.N + BI - 1) / BI;
-            // row I: one diagonal item, then ceil((N - (I+1) BI) / JC) chunks
+            // row I: ND diagonal items, then ceil((N - (I+1) BI) / JC) chunks
             int64_t items = 0;
             for (int64_t I = 0; I < g.nIB; ++I) {
                 rowoff[g.row_base + I] = items;
                 int64_t rest = g.N - (I + 1) * BI;
-                items += 1 + (rest > 0 ? (rest + JC - 1) / JC : 0);
+                items += ND + (rest > 0 ? (rest + JC - 1) / JC : 0);
             }
             rowoff[g.row_base + g.nIB] = items;
             g.items = items;
@@ -313,6 +313,7 @@ struct PairArgs {
     int nD, nS, S, K;   // S: LDS row stride (n_sigma + 1); K: rows held in LDS
     int JC;             // j-points per off-diagonal item (multiple of 64)
     int BI;             // i-points per row block (IPL x threads of the variant)
+    int ND;             // diagonal items per row block (j sub-ranges of BI / ND points)
     double tDmax;       // n_D - 1: table branch iff t_D = D / dD < n_D - 1
     double tSclamp;     // largest value below n_sigma - 1 (sigma index clamp)
     double csig;        // sqrt(n_sigma - 1)
@@ -759,10 +760,12 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
         for (int p = 0; p < IPL; ++p) Sc[p] = SL[p] = Sq[p] = 0.0;
         const int nimg = IMG ? A.nimg : 1;
 
-        if (c == 0) {
-            // diagonal item: ordered pairs inside the row block, j through scalar loads
-            const int j0 = I * BI, j1 = min(N, j0 + BI);
-            for (int L = 0; L < nimg; ++L) {
+        if (c < A.ND) {
+            // diagonal item c: ordered pairs of the row block's points with its
+            // c-th j sub-range, j through scalar loads
+            const int DS = BI / A.ND;
+            const int j0 = I * BI + c * DS, j1 = min(N, j0 + DS);
+            for (int L = 0; L < (j0 < j1 ? nimg : 0); ++L) {
                 R sx[IPL], sy[IPL], sz[IPL], mx[IPL], my[IPL], mz[IPL], wi[IPL];
                 bool home = true;
                 R lx = 0, ly = 0, lz = 0;
@@ -824,7 +827,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
             }
         } else {
             // off-diagonal item: both orders of every pair, j tiles rotating through the lanes
-            const int J0 = (I + 1) * BI + (c - 1) * A.JC, J1 = min(N, J0 + A.JC);
+            const int J0 = (I + 1) * BI + (c - A.ND) * A.JC, J1 = min(N, J0 + A.JC);
             const bool prune = IMG && A.rc2 < 1e300;
             R ib[6] = {0, 0, 0, 0, 0, 0};
             if (prune) {
@@ -941,7 +944,7 @@ struct FinArgs {
     const void *jpart;
     int jfp64;
     int64_t istride, jstride;
-    int JC, BI, NI, NJ;
+    int JC, BI, ND, NI, NJ;
     int img, adj, self_term;
     const int32_t *gidx;
     const double *n, *q0, *dqdn;
@@ -984,7 +987,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         double S0c = 0.0, S0L = 0.0, Sq = 0.0;
         const int iL = 1, iq = F.NI - 1;
         const int64_t *ro = F.rowoff + sg.row_base;
-        // as an i-point: the diagonal item and the chunks of its own row block
+        // as an i-point: the diagonal items and the chunks of its own row block
         const int64_t Bk = lp / F.BI, t = lp - Bk * F.BI;
         for (int64_t it = ro[Bk]; it < ro[Bk + 1]; ++it) {
             const int64_t k = (sg.slot_base + it) * F.BI + t;
@@ -996,7 +999,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         for (int64_t I = 0; I < Bk; ++I) {
             const int64_t off = lp - (I + 1) * F.BI;
             const int64_t cc = off / F.JC;
-            const int64_t k = (sg.slot_base + ro[I] + 1 + cc) * F.JC + (off - cc * F.JC);
+            const int64_t k = (sg.slot_base + ro[I] + F.ND + cc) * F.JC + (off - cc * F.JC);
             if (F.jfp64) {
                 const double *jp = (const double *)F.jpart;
                 S0c += jp[k];
@@ -1176,34 +1179,51 @@ struct Plan {
     int mimg[3] = {0, 0, 0};  // image range per axis (0 on open axes)
     bool img = false;
     int JC = 8192;
+    int tpb = kPairThreads;     // pair-kernel workgroup size
     int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
+    int ND = 1;                 // diagonal items per row block
     int NI = 1, NJ = 1;
     Layout L;
 };
 
-// i-points per lane of the pair-kernel variant these options select: four
-// for the FP32 n_sigma = 64 kernels without images, two elsewhere.  (With
-// images, four points per lane was measured slower on the slab: the wider
-// i box of a wavefront lets fewer tiles skip or run unmasked against the
-// cut, and the per-image set-up spills registers.)
+// i-points per lane of the pair-kernel variant these options select in
+// 1024-thread workgroups: four for the FP32 n_sigma = 64 kernels without
+// images, two elsewhere.  (With images, four points per lane was measured
+// slower on the slab: the wider i box of a wavefront lets fewer tiles skip
+// or run unmasked against the cut, and the per-image set-up spills
+// registers.)
 int ipl_for(int fp64, int kahan, int nsig, bool img) { return (!fp64 && !kahan && nsig == 64 && !img) ? 4 : 2; }
+
+// Work items of one density's list if every point were kept (an upper
+// bound for any density on that grid): per row block ND diagonal items and
+// the chunks of the points after it.
+int64_t items_bound(int64_t G, int64_t BI, int64_t JC, int64_t ND)
+{
+    const int64_t nib = (G + BI - 1) / BI;
+    int64_t items = 0;
+    for (int64_t I = 0; I < nib; ++I) {
+        const int64_t rest = G - (I + 1) * BI;
+        items += ND + (rest > 0 ? (rest + JC - 1) / JC : 0);
+    }
+    return items;
+}
+
+// Diagonal items per row block: a diagonal item evaluates each ordered pair
+// on its own (twice the work per pair of the two-sided off-diagonal rings),
+// so BI x BI / ND ordered pairs cost about as much as one BI x JC chunk
+// when ND = BI / JC.
+int diag_items(int64_t BI, int64_t JC) { return BI > JC ? (int)(BI / JC) : 1; }
+
+// Compute units of the target (gfx950): the pair kernel runs one persistent
+// workgroup per CU, so the work list needs many more items than this to
+// keep every CU busy to the end.
+constexpr int64_t kCUs = 256;
 
 int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int nsig, int fp64, int adj,
               Plan *P)
 {
     P->segs.resize(B);
-    P->JC = o->j_chunks > 0 ? 1024 * o->j_chunks : 8192;
-    const int64_t JC = P->JC;
-    {
-        // the image loop runs when a periodic axis has images or a cut is set
-        int nimg = 1;
-        for (int a = 0; a < 3; ++a)
-            if (grids[0].periodic[a] && o->image_max[a] > 0) nimg *= 2 * o->image_max[a] + 1;
-        const bool img = nimg > 1 || o->r_cut > 0.0;
-        P->BI = ipl_for(fp64, o->kahan, nsig, img) * kPairThreads;
-    }
-    const int64_t BI = P->BI;
-    int64_t t_off = 0, slots = 0, rows = 0, fin = 0, Gtot = 0;
+    int64_t Gtot = 0;
     for (int b = 0; b < B; ++b) {
         GridDev g;
         int rc = validate_grid(&grids[b], &g);
@@ -1226,27 +1246,65 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         s.grid_off = grid_off ? grid_off[b] : 0;
         if (grid_off && grid_off[b + 1] - grid_off[b] != g.G)
             return fail(VDW_EINVAL, "grid_off[%d+1] - grid_off[%d] != grid %d size", b, b, b);
-        s.nbx = (g.nx + 3) / 4;
-        s.nby = (g.ny + 3) / 4;
-        s.nbz = (g.nz + 3) / 4;
+        Gtot += g.G;
+    }
+    if (Gtot > ((int64_t)1 << 31) - 1) return fail(VDW_EINVAL, "total grid size exceeds 2^31 - 1");
+    auto bound = [&](int64_t BI, int64_t JC) {
+        int64_t n = 0;
+        for (int b = 0; b < B; ++b) n += items_bound(P->segs[b].G, BI, JC, diag_items(BI, JC));
+        return n;
+    };
+    {
+        // the image loop runs when a periodic axis has images or a cut is set
+        int nimg = 1;
+        for (int a = 0; a < 3; ++a)
+            if (grids[0].periodic[a] && o->image_max[a] > 0) nimg *= 2 * o->image_max[a] + 1;
+        const bool img = nimg > 1 || o->r_cut > 0.0;
+        const bool fast = !fp64 && !o->kahan && nsig == 64;
+        // workgroup shape: 512 threads with eight i-points per lane on request
+        // (FP32 n_sigma = 64 kernels without images); 256 threads with two on
+        // request or, by default, when even the finest chunking of the
+        // 1024-thread list leaves half the CUs idle (no images); else 1024
+        const int64_t BI_big = (int64_t)ipl_for(fp64, o->kahan, nsig, img) * kPairThreads;
+        if (fast && !img && o->block_threads == 512) {
+            P->tpb = 512;
+            P->BI = 8 * 512;
+        } else if (!img && (o->block_threads == 256 || (o->block_threads == 0 && bound(BI_big, 1024) < kCUs / 2))) {
+            P->tpb = 256;
+            P->BI = 2 * 256;
+        } else {
+            P->tpb = kPairThreads;
+            P->BI = (int)BI_big;
+        }
+        // chunk length: as requested, or the longest of 8192 ... 1024 points
+        // that still gives 16 items per CU when every point is kept (the
+        // last items to finish then leave little of the launch idle)
+        if (o->j_chunks > 0) {
+            P->JC = 1024 * o->j_chunks;
+        } else {
+            P->JC = 8192;
+            while (P->JC > 1024 && bound(P->BI, P->JC) < 16 * kCUs) P->JC /= 2;
+        }
+    }
+    P->ND = diag_items(P->BI, P->JC);
+    const int64_t BI = P->BI, JC = P->JC;
+    int64_t t_off = 0, slots = 0, rows = 0, fin = 0;
+    for (int b = 0; b < B; ++b) {
+        Seg &s = P->segs[b];
+        s.nbx = (s.nx + 3) / 4;
+        s.nby = (s.ny + 3) / 4;
+        s.nbz = (s.nz + 3) / 4;
         int64_t T = (int64_t)s.nbx * s.nby * s.nbz * 64;
         s.T = (T + kCompactBlock - 1) / kCompactBlock * kCompactBlock;
         s.t_off = t_off;
         t_off += s.T;
-        // work items if every point were kept (an upper bound for any density)
-        int64_t nib = (g.G + BI - 1) / BI, items = 0;
-        for (int64_t I = 0; I < nib; ++I) {
-            int64_t rest = g.G - (I + 1) * BI;
-            items += 1 + (rest > 0 ? (rest + JC - 1) / JC : 0);
-        }
+        const int64_t nib = (s.G + BI - 1) / BI;
         s.row_base = rows;
         rows += nib + 1;
         s.slot_base = slots;
-        slots += items;
-        fin += (g.G + kFinThreads - 1) / kFinThreads;
-        Gtot += g.G;
+        slots += items_bound(s.G, BI, JC, P->ND);
+        fin += (s.G + kFinThreads - 1) / kFinThreads;
     }
-    if (Gtot > ((int64_t)1 << 31) - 1) return fail(VDW_EINVAL, "total grid size exceeds 2^31 - 1");
     // images on periodic axes
     int m[3];
     for (int a = 0; a < 3; ++a) {
@@ -1317,8 +1375,8 @@ int validate_opts(const vdw_opts *o)
     if (!(o->n_cut > 0.0) || !isfinite(o->n_cut)) return fail(VDW_EINVAL, "n_cut must be > 0");
     if (o->precision != VDW_FP64 && o->precision != VDW_FP32C) return fail(VDW_EINVAL, "precision must be 0 or 1");
     if (o->self_term != 0 && o->self_term != 1) return fail(VDW_EINVAL, "self_term must be 0 or 1");
-    if (o->block_threads != 0 && o->block_threads != 1024 && o->block_threads != 512)
-        return fail(VDW_EINVAL, "block_threads must be 0, 512 or 1024");
+    if (o->block_threads != 0 && o->block_threads != 1024 && o->block_threads != 512 && o->block_threads != 256)
+        return fail(VDW_EINVAL, "block_threads must be 0, 256, 512 or 1024");
     if (o->j_chunks < 0 || o->j_chunks > 64) return fail(VDW_EINVAL, "j_chunks must be in 0..64");
     if (o->grid_blocks < 0) return fail(VDW_EINVAL, "grid_blocks must be >= 0");
     if (o->kahan != 0 && o->kahan != 1) return fail(VDW_EINVAL, "kahan must be 0 or 1");
@@ -1358,16 +1416,23 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 // in 1024-thread workgroups, or eight in 512-thread ones), FP32C for any
 // n_sigma, Kahan-compensated FP32C, and plain FP64 (two per lane, 1024
 // threads); each with and without the adjoint sums and the image loop.
+// Without images every one of them also has 256-thread workgroups with two
+// i-points per lane, for work lists too short to occupy every CU.
 template <typename R, bool KAHAN, int NSIG, bool CUBIC>
 int launch_pair_v(int adj, int img, int tpb, const PairArgs &a, const PairPtrs &p, int grid, size_t lds,
                   hipStream_t s, bool attr_only)
 {
     constexpr bool FAST = sizeof(R) == 4 && !KAHAN && NSIG == 64;
+    if (!img && tpb == 256)
+        return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, 2, 256>(a, p, grid, lds, s, attr_only)
+                   : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, 2, 256>(a, p, grid, lds, s, attr_only);
     if (img) return adj ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC, 2, 1024>(a, p, grid, lds, s, attr_only)
                         : launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC, 2, 1024>(a, p, grid, lds, s, attr_only);
-    if (FAST && tpb == 512)
-        return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only)
-                   : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only);
+    if constexpr (FAST) {
+        if (tpb == 512)
+            return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only)
+                       : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only);
+    }
     constexpr int W = FAST ? 4 : 2;
     return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, W, 1024>(a, p, grid, lds, s, attr_only)
                : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, W, 1024>(a, p, grid, lds, s, attr_only);
@@ -1432,9 +1497,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
         return fail(VDW_EUNSUPPORTED, "the pair kernel needs %d bytes of LDS per workgroup (device: %zu)", kLdsBytes,
                     dev.lds_per_block);
     // table rows that fit in the kernel's static LDS next to its reduction buffer
-    // 512-thread workgroups (eight i-points per lane) on request for the FP32
-    // n_sigma = 64 kernels without images; 1024 everywhere else
-    E->tpb = (!E->fp64 && !E->kahan && tp->n_sigma == 64 && !P.img && o->block_threads == 512) ? 512 : 1024;
+    E->tpb = P.tpb;
     const int cap = E->fp64 ? tab_elems<double>(P.NJ, E->tpb / 64) : tab_elems<float>(P.NJ, E->tpb / 64);
     int K = cap / S;
     if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
@@ -1457,6 +1520,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.K = K;
     pa.JC = P.JC;
     pa.BI = P.BI;
+    pa.ND = P.ND;
     pa.csig = sqrt((double)(tp->n_sigma - 1));
     pa.tDmax = (double)(tp->n_D - 1);
     pa.tSclamp = E->fp64 ? nextafter((double)(tp->n_sigma - 1), 0.0)
@@ -1536,7 +1600,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)L.nblocks), dim3(kCompactThreads), 0, s, (const Seg *)segs, B,
                        n_d, E.n_cut, counts, flag);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, counts, L.nblocks, segs, B, hdr, rowoff,
-                       (int64_t)P.JC, (int64_t)P.BI);
+                       (int64_t)P.JC, (int64_t)P.BI, (int64_t)P.ND);
     ScatterArgs sa;
     sa.segs = segs;
     sa.B = B;
@@ -1582,6 +1646,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.jstride = E.pa.jstride;
     fa.JC = P.JC;
     fa.BI = P.BI;
+    fa.ND = P.ND;
     fa.NI = P.NI;
     fa.NJ = P.NJ;
     fa.img = P.img ? 1 : 0;
@@ -1639,6 +1704,7 @@ void set_stats(const Exec &E, const double *host, float ms)
     g_stats.block_threads = E.tpb;
     g_stats.j_chunks = E.P.JC / 1024;
     g_stats.grid_blocks = E.grid;
+    g_stats.diag_items = E.P.ND;
 }
 
 // The whole pipeline for B densities, energies read back to the host.

@@ -1,8 +1,8 @@
 """The autotuner: it times each (workgroup shape, j-chunk length) candidate
 with the pair kernel's HIP events, keeps the fastest, caches the choice, and
 the tuned evaluation gives the same result (the tile shape changes the
-summation order only).  The FP64 kernel has one workgroup shape, so only
-its chunk lengths are swept; the FP32C sweep covers both shapes."""
+summation order only).  The FP64 kernel has the 1024- and 256-thread
+shapes; the FP32C n_sigma = 64 sweep covers 1024, 512 and 256."""
 import json
 
 import pytest
@@ -36,10 +36,11 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch):
 
     base = V.Opts(n_cut=wl.n_cut, precision=0)
     tuned = autotune.tune(run, base, kept=kept, candidates=(1, 2, 4, 8), repeats=1, verbose=True)
-    assert tuned.j_chunks in (1, 2, 4, 8) and tuned.block_threads == 1024
+    assert tuned.j_chunks in (1, 2, 4, 8) and tuned.block_threads in (1024, 256)
     data = json.loads(cache.read_text())
     (entry,) = data.values()
-    assert entry["j_chunks"] == tuned.j_chunks and set(entry["sweep"]) == {"1024/1", "1024/2", "1024/4", "1024/8"}
+    assert entry["j_chunks"] == tuned.j_chunks
+    assert set(entry["sweep"]) == {f"{bt}/{jc}" for bt in (1024, 256) for jc in (1, 2, 4, 8)}
     assert min(entry["sweep"].values()) == entry["ms"] > 0
     # the cached choice comes back without timing
     again = autotune.tune(lambda o: pytest.fail("re-timed a cached workload"), base, kept=kept)
@@ -49,9 +50,10 @@ def test_autotune_picks_and_caches(tmp_path, monkeypatch):
     assert sum(E1) == pytest.approx(sum(E0), rel=1e-12)
     assert float(torch.linalg.norm(v1 - v0) / torch.linalg.norm(v0)) <= 1e-12
     assert V.last_stats()["j_chunks"] == tuned.j_chunks
-    # FP32C on the same cubic dimer and 64-column table: both shapes are timed
+    assert V.last_stats()["block_threads"] == tuned.block_threads
+    # FP32C on the same cubic dimer and 64-column table: all three shapes are timed
     f32 = autotune.tune(run, V.Opts(n_cut=wl.n_cut, precision=1), kept=kept, candidates=(4, 8), repeats=1,
                         verbose=True)
     sweep = next(e for k, e in json.loads(cache.read_text()).items() if "|p1|" in k)["sweep"]
-    assert set(sweep) == {"1024/4", "1024/8", "512/4", "512/8"}
-    assert f32.block_threads in (1024, 512)
+    assert set(sweep) == {f"{bt}/{jc}" for bt in (1024, 512, 256) for jc in (4, 8)}
+    assert f32.block_threads in (1024, 512, 256)

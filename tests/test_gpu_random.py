@@ -3,7 +3,8 @@
 FP32C forms): grid shapes and spacings (cubic or not), periodic axes and
 image ranges, distance cuts, table shapes (16 or 64 sigma columns, so both
 the generic and the fast kernels run), LDS row limits, j-chunk lengths and
-workgroup shapes.  A random cut is moved off any pair distance it would
+workgroup shapes (with short chunks, 1024-thread row blocks split their
+diagonal work into several items).  A random cut is moved off any pair distance it would
 nearly tie with (a tie may fall either way in FP32)."""
 import numpy as np
 import pytest
@@ -68,7 +69,7 @@ def _case(k):
     if rng.random() < 0.4:
         wl.r_cut = _safe_cut(rng, h)
     opts = dict(table_lds_rows=int(rng.choice([-1, 2, 12, 60])), j_chunks=int(rng.choice([0, 1, 2])),
-                block_threads=int(rng.choice([0, 512])))
+                block_threads=int(rng.choice([0, 256, 512, 1024])))
     nS = int(rng.choice([16, 64]))
     return wl, opts, nS
 
@@ -99,7 +100,7 @@ def test_random_configuration(V, oracle, tables, k):
         rel_v = np.linalg.norm(v - ref.dEdn) / np.linalg.norm(ref.dEdn)
         say(f"case {k} prec {prec}: n={wl.n} h={tuple(round(x, 3) for x in wl.h)} per={wl.periodic} "
             f"img={wl.image_max} rc={wl.r_cut:.3f} nS={nS} {extra} N={st['retained']} "
-            f"threads={st['block_threads']} dE={rel_e:.1e} dv={rel_v:.1e}")
+            f"threads={st['block_threads']} diag={st['diag_items']} dE={rel_e:.1e} dv={rel_v:.1e}")
         assert rel_e <= etol
         for a, b in ((E[0], ref.E_pair0), (E[1], ref.E_pairL), (E[2], ref.E_self)):
             assert abs(a - b) <= etol * abs(ref.E) + 1e-300

@@ -4,7 +4,9 @@ size or not at all, element by element against the oracle (energies 1e-12 /
 
 * four i-points per lane on a non-cubic grid (difference form of r^2), and
   eight per lane in 512-thread workgroups on cubic and non-cubic grids;
-* the Kahan-compensated FP32 variant;
+* the Kahan-compensated FP32 variant, in 1024- and 256-thread workgroups;
+* row blocks whose diagonal work is split into several items (chunks
+  shorter than the row block);
 * a cubic periodic grid whose image-shifted coordinates are too large for
   the exact integer form of r^2 (|x_i|^2 + |x_j|^2 alone passes 2^24 for
   neighbouring points), which the host must route to the difference form.
@@ -78,8 +80,8 @@ def test_non_cubic_grid_four_points_per_lane(V, oracle, big, prec):
     seven row blocks of 4096 (FP32C) with a ragged last one."""
     tp, tab = big
     wl = W.random_small(n=(34, 30, 28), h=(0.40, 0.45, 0.35), seed=21, n_cut=1e-3)
-    st = _run_check(V, oracle, wl, tp, tab, prec, "non-cubic")
-    assert st["retained"] > 4 * 4096 and st["retained"] % 4096 != 0
+    st = _run_check(V, oracle, wl, tp, tab, prec, "non-cubic", block_threads=1024)
+    assert st["retained"] > 4 * 4096 and st["retained"] % 4096 != 0 and st["block_threads"] == 1024
 
 
 @pytest.mark.parametrize("cubic", [True, False])
@@ -99,11 +101,28 @@ def test_eight_points_per_lane(V, oracle, big, cubic):
     assert st["block_threads"] == 512
 
 
-def test_kahan_variant(V, oracle, big):
-    """kahan = 1 (every FP32 run Kahan-compensated) on a 30^3 dimer."""
+@pytest.mark.parametrize("threads", [1024, 256])
+def test_kahan_variant(V, oracle, big, threads):
+    """kahan = 1 (every FP32 run Kahan-compensated) on a 30^3 dimer, in both
+    workgroup shapes the Kahan kernel has."""
     tp, tab = big
     wl = W.scaled_dimer(edge=30, h=0.4, R=5.0)
-    _run_check(V, oracle, wl, tp, tab, "fp32c", "kahan", kahan=1)
+    st = _run_check(V, oracle, wl, tp, tab, "fp32c", "kahan", kahan=1, block_threads=threads)
+    assert st["block_threads"] == threads
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+@pytest.mark.parametrize("jc", [1, 2])
+def test_split_diagonal(V, oracle, big, prec, jc):
+    """1024-thread row blocks with chunks shorter than the block: each row
+    block's diagonal work is split into BI / JC items (two or four; one for
+    FP64 blocks of 2048 with chunks of 2048), on the non-cubic grid with a
+    ragged last block."""
+    tp, tab = big
+    wl = W.random_small(n=(34, 30, 28), h=(0.40, 0.45, 0.35), seed=23, n_cut=1e-3)
+    st = _run_check(V, oracle, wl, tp, tab, prec, f"split diagonal jc={jc}", block_threads=1024, j_chunks=jc)
+    bi = 2048 if prec == "fp64" else 4096
+    assert st["diag_items"] == max(1, bi // (1024 * jc))
 
 
 def test_large_coordinates_use_the_difference_form(V, oracle, big):
