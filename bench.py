@@ -41,13 +41,13 @@ PEAK_FP32_TFLOPS = 157.3
 # instructions against wave64 issue slots from GRBM_GUI_ACTIVE); reported
 # beside the live roofline, not measured by this script.
 PROFILE_COUNTERS = {
-    "kr": {"source": "profiles/pair_kernel_kr_scan96_fp32c.md", "executed_tflops": 47.3, "executed_frac": 0.301,
+    "kr": {"source": "profiles/pair_kernel_kr_scan96_fp32c.md", "executed_tflops": 47.5, "executed_frac": 0.302,
            "valu_instructions_per_issue_slot": 1.11, "lane_instructions_per_unordered_pair": 39.9},
 }
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
-TRAFFIC_BYTES = {"kr": (5049320.125 * 2.0 + 6034241.21875) * 1024}
+TRAFFIC_BYTES = {"kr": (5055168.3125 * 2.0 + 6034241.21875) * 1024}
 
 
 def parse():

@@ -313,7 +313,7 @@ struct PairArgs {
     int nD, nS, S, K;   // S: LDS row stride (n_sigma + 1); K: rows held in LDS
     int JC;             // j-points per off-diagonal item (multiple of 64)
     int BI;             // i-points per row block (IPL x threads of the variant)
-    int ND;             // diagonal items per row block (j sub-ranges of BI / ND points)
+    int ND, DS;         // diagonal items per row block, each over a j sub-range of DS = BI / ND points
     double tDmax;       // n_D - 1: table branch iff t_D = D / dD < n_D - 1
     double tSclamp;     // largest value below n_sigma - 1 (sigma index clamp)
     double csig;        // sqrt(n_sigma - 1)
@@ -763,8 +763,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
         if (c < A.ND) {
             // diagonal item c: ordered pairs of the row block's points with its
             // c-th j sub-range, j through scalar loads
-            const int DS = BI / A.ND;
-            const int j0 = I * BI + c * DS, j1 = min(N, j0 + DS);
+            const int j0 = I * BI + c * A.DS, j1 = min(N, j0 + A.DS);
             for (int L = 0; L < (j0 < j1 ? nimg : 0); ++L) {
                 R sx[IPL], sy[IPL], sz[IPL], mx[IPL], my[IPL], mz[IPL], wi[IPL];
                 bool home = true;
@@ -1521,6 +1520,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.JC = P.JC;
     pa.BI = P.BI;
     pa.ND = P.ND;
+    pa.DS = P.BI / P.ND;
     pa.csig = sqrt((double)(tp->n_sigma - 1));
     pa.tDmax = (double)(tp->n_D - 1);
     pa.tSclamp = E->fp64 ? nextafter((double)(tp->n_sigma - 1), 0.0)
