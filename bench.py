@@ -325,6 +325,28 @@ def main():
         out["energy_only"] = {"value": pairs * steps_e / dte, "ms_per_step": 1e3 * dte / steps_e,
                               "dE_rel_max_vs_fused": max(abs(sum(x) - sum(y)) / abs(sum(y)) for x, y in zip(Ee, E32))}
         p.close()
+    if a.workload == "batch":
+        # the same step as one call per density (q0, then energy + potential),
+        # each with its own automatic tile shape
+        def singles():
+            res = []
+            for b, gb in enumerate(grids):
+                nb = n[offs[b]:offs[b + 1]]
+                qb = V.compute_q0(gb, nb, wls[b].n_cut)
+                res.append(V.enl_potential(gb, nb, qb, table, opts(main_prec))[0])
+            return res
+        singles()
+        torch.cuda.synchronize()
+        steps_s = max(1, a.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps_s):
+            Es = singles()
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0
+        out["single_calls"] = {"value": pairs * steps_s / dts, "ms_per_step": 1e3 * dts / steps_s,
+                               "batched_speedup": (pairs * a.steps / dt) / (pairs * steps_s / dts),
+                               "dE_rel_max_vs_batched": max(abs(sum(x) - sum(y)) / abs(sum(y))
+                                                            for x, y in zip(Es, E32))}
     if not a.no_cpu_baseline and a.workload in ("kr", "kr1"):
         cb = cpu_baseline(W.kr_dimer(7.0) if a.workload == "kr" else wl, a.cpu_rows)
         cb["per_core"] = cb["value"] / cb["cores"]
