@@ -4,9 +4,10 @@ Plain FP64 CPU reference of everything the GPU library computes.  It is
 written from the mathematics of Lazic et al. (arXiv:0810.2273), Sec. 2
 (Eqs. 1-2, the kernel of Dion et al. and its large-D asymptote), Sec. 3
 (gradient, density cut-off, 0th cell plus periodic repetition), and from
-the two published ingredients that paper builds on: the Dion et al. q0
-(LDA exchange-correlation plus gradient term) and the Perdew-Wang 1992
-LDA correlation.  The heavy loops (quadrature of the kernel, the double
+the published ingredients that paper builds on: the Dion et al. q0
+(LDA exchange-correlation plus gradient term), the Perdew-Wang 1992 LDA
+correlation, and the PBE and revPBE exchange and PBE correlation energies
+that enter the recombination of Eq. (3).  The heavy loops (quadrature of the kernel, the double
 sum) live in vdw_oracle.c; the O(grid) steps are numpy/scipy here.
 
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may use
@@ -336,6 +337,78 @@ def compute_q0(grid: Grid, rho, n_cut):
     qq, a, b = q0_of(r[keep], g[keep])
     q[keep], dqdn[keep], dqdg[keep] = qq, a, b
     return dict(gx=gx, gy=gy, gz=gz, g=g, q0=q, dq_dn=dqdn, dq_dg=dqdg, keep=keep)
+
+
+# --------------------------------------------------------------------------
+# Local and semilocal exchange-correlation energies and the recombination of
+# Eq. (3).  The paper's code evaluates these from the same density (Sec. 3,
+# the list of steps; Sec. 5 sample output), with the PBE and revPBE forms of
+# the works it cites.  Spin-unpolarised, Hartree units.
+# --------------------------------------------------------------------------
+
+PBE_KAPPA = 0.804        # PBE exchange: upper bound of the enhancement is 1 + kappa
+REVPBE_KAPPA = 1.245     # revPBE (Zhang and Yang): the same form with a larger kappa
+PBE_BETA = 0.06672455060314922                   # gradient-expansion coefficient of correlation
+PBE_MU = PBE_BETA * math.pi ** 2 / 3.0           # exchange coefficient that cancels it at small s
+PBE_GAMMA = (1.0 - math.log(2.0)) / math.pi ** 2
+
+
+def lda_eps_x(n):
+    """Exchange energy per electron of the uniform gas: -3 k_F / (4 pi)."""
+    kF = np.cbrt(3.0 * math.pi ** 2 * np.asarray(n, dtype=np.float64))
+    return -3.0 * kF / (4.0 * math.pi)
+
+
+def pbe_fx(s2, kappa=PBE_KAPPA):
+    """Exchange enhancement F_x(s) = 1 + kappa - kappa / (1 + mu s^2 / kappa)."""
+    s2 = np.asarray(s2, dtype=np.float64)
+    return 1.0 + kappa - kappa / (1.0 + PBE_MU * s2 / kappa)
+
+
+def pbe_h(rs, t2):
+    """Gradient correction H(r_s, t) of PBE correlation (unpolarised):
+    H = gamma ln(1 + (beta/gamma) t^2 (1 + A t^2) / (1 + A t^2 + A^2 t^4)),
+    A = (beta/gamma) / (exp(-eps_c/gamma) - 1)."""
+    rs = np.asarray(rs, dtype=np.float64)
+    t2 = np.asarray(t2, dtype=np.float64)
+    ec, _ = pw92_ec(rs)
+    A = (PBE_BETA / PBE_GAMMA) / np.expm1(-ec / PBE_GAMMA)
+    y = A * t2
+    return PBE_GAMMA * np.log1p((PBE_BETA / PBE_GAMMA) * t2 * (1.0 + y) / (1.0 + y + y * y))
+
+
+def xc_energies(grid: Grid, rho, n_floor: float):
+    """E_x^LDA, E_c^LDA (PW92), E_x^PBE, E_c^PBE, E_x^revPBE: dV times the sum
+    over grid points with n > n_floor of n eps(n, |grad n|), the gradient by
+    the finite differences of Sec. 3.  s = |grad n| / (2 k_F n), t = |grad n|
+    / (2 k_s n), k_s = sqrt(4 k_F / pi)."""
+    r = np.asarray(rho, dtype=np.float64).reshape(-1)
+    gx, gy, gz = gradient(grid, r)
+    keep = r > n_floor
+    n = r[keep]
+    g2 = (gx * gx + gy * gy + gz * gz)[keep]
+    kF = np.cbrt(3.0 * math.pi ** 2 * n)
+    rs = np.cbrt(3.0 / (4.0 * math.pi * n))
+    ks2 = 4.0 * kF / math.pi
+    ex = lda_eps_x(n)
+    ec, _ = pw92_ec(rs)
+    s2 = g2 / (2.0 * kF * n) ** 2
+    t2 = g2 / (4.0 * ks2 * n * n)
+    dV = grid.dV
+    return dict(Ex_lda=dV * np.sum(n * ex), Ec_lda=dV * np.sum(n * ec),
+                Ex_pbe=dV * np.sum(n * ex * pbe_fx(s2, PBE_KAPPA)), Ec_pbe=dV * np.sum(n * (ec + pbe_h(rs, t2))),
+                Ex_revpbe=dV * np.sum(n * ex * pbe_fx(s2, REVPBE_KAPPA)))
+
+
+def recombine(E_nl, Ec_lda, Ec_pbe, Ex_pbe=None, Ex_new=None, E_dft=None):
+    """Eq. (3): E_tot^NL = E_tot^DFT - E_x^PBE - E_c^PBE + (E_x + E_c^LDA + E_c^NL),
+    E_x being E_x^PBE or E_x^revPBE (Ex_new).  Without E_tot^DFT, the part
+    that does not need it, -E_c^PBE + E_c^LDA + E_c^NL (+ E_x^new - E_x^PBE
+    when an exchange is given), the sum the sample output prints."""
+    delta = -Ec_pbe + Ec_lda + E_nl
+    if Ex_new is not None:
+        delta += Ex_new - Ex_pbe
+    return delta if E_dft is None else E_dft + delta
 
 
 # --------------------------------------------------------------------------
