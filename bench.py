@@ -325,6 +325,19 @@ def main():
         out["energy_only"] = {"value": pairs * steps_e / dte, "ms_per_step": 1e3 * dte / steps_e,
                               "dE_rel_max_vs_fused": max(abs(sum(x) - sum(y)) / abs(sum(y)) for x, y in zip(Ee, E32))}
         p.close()
+    if a.workload == "kr":
+        # the exchange-correlation energies of Eq. (3) for the scan's densities
+        # (outside the timed step; one call per density, each ending in a host wait)
+        xcs = [V.xc_energies(gb, n[offs[b]:offs[b + 1]]) for b, gb in enumerate(grids)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xcs = [V.xc_energies(gb, n[offs[b]:offs[b + 1]]) for b, gb in enumerate(grids)]
+        dtx = time.perf_counter() - t0
+        e_nl = [sum(e) for e in E32]
+        out["xc_energies"] = {"ms_per_density": 1e3 * dtx / len(grids), "grid_points": int(offs[1] - offs[0]),
+                              "R7_dimer": dict(xcs[3], E_nl=e_nl[3],
+                                               correction_pbe=V.recombine(xcs[3], e_nl[3], 0.0, "pbe"),
+                                               correction_revpbe=V.recombine(xcs[3], e_nl[3], 0.0, "revpbe"))}
     if a.workload == "batch":
         # the same step as one call per density (q0, then energy + potential),
         # each with its own automatic tile shape

@@ -156,6 +156,41 @@ int build_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, voi
 int compute_q0(const vdw_grid *grid, double n_cut, const double *n_d, double *grad_d, double *q0_d,
                double *dq_dn_d, double *dq_dg_d, void *stream);
 
+/* ---------------------------------------------------------------------
+ * xc_energies -- the local and semilocal exchange-correlation energies that
+ * the recombination of Eq. (3) needs (the paper's code evaluates them from
+ * the same density, Sec. 3), spin-unpolarised, in Hartree:
+ *   E[0] E_x^LDA     = dV sum n eps_x,           eps_x = -3 k_F / (4 pi)
+ *   E[1] E_c^LDA     = dV sum n eps_c^PW92(r_s)
+ *   E[2] E_x^PBE     = dV sum n eps_x F_x(s),    F_x = 1 + k - k / (1 + mu s^2 / k),
+ *                      k = 0.804, mu = beta pi^2 / 3, s = |grad n| / (2 k_F n)
+ *   E[3] E_c^PBE     = dV sum n (eps_c^PW92 + H(r_s, t)),
+ *                      H = gamma ln(1 + (beta/gamma) t^2 (1 + A t^2) / (1 + A t^2 + A^2 t^4)),
+ *                      A = (beta/gamma) / (exp(-eps_c/gamma) - 1), t = |grad n| / (2 k_s n),
+ *                      k_s = sqrt(4 k_F / pi), beta = 0.06672455060314922, gamma = (1 - ln 2) / pi^2
+ *   E[4] E_x^revPBE  = E_x^PBE with k = 1.245
+ * over the grid points with n > n_floor (others, negative densities
+ * included, add nothing); grad n as in compute_q0.
+ *   n_d:     device, G doubles (read).
+ *   n_floor: finite, >= 0 (1e-12 is a safe choice: near n = 0 the gradient
+ *            terms overflow).
+ *   ws:      device workspace of xc_workspace_size(grid) bytes.
+ *   E:       host, 5 doubles, written after `stream` has been synchronised.
+ * Errors: VDW_EINVAL (null pointers, n_floor < 0 or not finite, bad grid),
+ * VDW_EUNSUPPORTED (non-orthorhombic cell), VDW_EWORKSPACE, VDW_ENONFINITE
+ * (an energy is not finite; E is still written), VDW_EHIP.
+ * ------------------------------------------------------------------- */
+size_t xc_workspace_size(const vdw_grid *grid);
+int xc_energies(const vdw_grid *grid, const double *n_d, double n_floor, void *ws, size_t ws_bytes, double *E,
+                void *stream);
+
+/* Eq. (3): E_tot^NL = E_tot^DFT - E_x^PBE - E_c^PBE + (E_x + E_c^LDA + E_c^NL),
+ * with E_x = E_x^PBE (exchange = 0) or E_x^revPBE (exchange = 1), E_xc the
+ * five energies of xc_energies and E_nl = E_pair0 + E_pairL + E_self.  With
+ * E_dft = 0 this is the correction to add to a PBE total energy.  NaN for a
+ * NULL E_xc or another exchange value. */
+double vdw_recombine(const double *E_xc, double E_nl, double E_dft, int32_t exchange);
+
 /* Bytes of device workspace enl_energy / enl_potential need for this grid
  * and these options (an upper bound that holds for any density). */
 size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, const vdw_opts *opts);

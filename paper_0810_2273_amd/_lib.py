@@ -25,7 +25,7 @@ EXPORTS = (
     "vdw_last_error", "vdw_version", "build_phi_table", "compute_q0", "enl_workspace_size", "enl_energy",
     "enl_potential", "enl_batched_workspace_size", "enl_potential_batched", "vdw_last_stats", "vdw_set_timing",
     "enl_batch_plan_create", "enl_batch_plan_execute", "enl_batch_plan_capture", "enl_batch_plan_replay",
-    "enl_batch_plan_destroy",
+    "enl_batch_plan_destroy", "xc_workspace_size", "xc_energies", "vdw_recombine",
 )
 
 
@@ -107,6 +107,12 @@ def lib():
     L.vdw_last_stats.argtypes = [P(VdwStats)]
     L.vdw_set_timing.restype = None
     L.vdw_set_timing.argtypes = [i32]
+    L.xc_workspace_size.restype = sz
+    L.xc_workspace_size.argtypes = [P(VdwGrid)]
+    L.xc_energies.restype = ct.c_int
+    L.xc_energies.argtypes = [P(VdwGrid), vp, d, vp, sz, P(d), vp]
+    L.vdw_recombine.restype = d
+    L.vdw_recombine.argtypes = [P(d), d, d, i32]
     _lib = L
     return L
 

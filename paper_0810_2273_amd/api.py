@@ -197,6 +197,37 @@ def enl_potential(grid: Grid, n: torch.Tensor, qd: dict, table: Table, opts: Opt
     return (float(E[0]), float(E[1]), float(E[2])), dEdn
 
 
+XC_TERMS = ("Ex_lda", "Ec_lda", "Ex_pbe", "Ec_pbe", "Ex_revpbe")
+
+
+def xc_workspace_size(grid: Grid) -> int:
+    g = grid.c()
+    return int(L.lib().xc_workspace_size(ct.byref(g)))
+
+
+def xc_energies(grid: Grid, n: torch.Tensor, n_floor: float = 1e-12, stream=None) -> dict:
+    """E_x^LDA, E_c^LDA, E_x^PBE, E_c^PBE and E_x^revPBE (Hartree) of the
+    density, over the grid points with n > n_floor."""
+    _f64(n, "n")
+    g = grid.c()
+    nbytes = int(L.lib().xc_workspace_size(ct.byref(g)))
+    if nbytes == 0:
+        raise L.VdwError(L.VDW_EINVAL, "invalid grid for xc_workspace_size")
+    ws = _workspace(nbytes, n.device)
+    E = (ct.c_double * 5)()
+    L.check(L.lib().xc_energies(ct.byref(g), _ptr(n), float(n_floor), _ptr(ws), ws.numel(), E, _stream(stream)))
+    return dict(zip(XC_TERMS, (float(x) for x in E)))
+
+
+def recombine(xc: dict, E_nl: float, E_dft: float = 0.0, exchange: str = "pbe") -> float:
+    """Eq. (3): E_dft - E_x^PBE - E_c^PBE + (E_x + E_c^LDA + E_nl), E_x the
+    PBE or revPBE exchange of `xc` (from xc_energies)."""
+    if exchange not in ("pbe", "revpbe"):
+        raise ValueError("exchange must be 'pbe' or 'revpbe'")
+    E = (ct.c_double * 5)(*(xc[k] for k in XC_TERMS))
+    return float(L.lib().vdw_recombine(E, float(E_nl), float(E_dft), 1 if exchange == "revpbe" else 0))
+
+
 def pack_batch(grids, ns):
     """Concatenate densities into one packed array with the offsets the batched call takes."""
     offs = [0]

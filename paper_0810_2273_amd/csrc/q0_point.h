@@ -1,7 +1,8 @@
-// Gradient and q0 of one grid point, shared by the single-grid kernel and the
-// batched one: second-order finite differences on perpendicular axes
-// (Sec. 3), q0 of Dion et al. from the LDA exchange, the Perdew-Wang 1992
-// correlation (its logarithm as log1p) and the gradient term; FP64.
+// Gradient and q0 of one grid point, shared by the single-grid kernel, the
+// batched one and the exchange-correlation energies: second-order finite
+// differences on perpendicular axes (Sec. 3), q0 of Dion et al. from the LDA
+// exchange, the Perdew-Wang 1992 correlation (its logarithm as log1p) and
+// the gradient term; FP64.
 #pragma once
 
 #include <math.h>
@@ -21,6 +22,23 @@ __device__ inline double fd_axis(const double *__restrict__ n, long idx, int i, 
     if (i == 0) return (-3.0 * n[idx] + 4.0 * n[idx + st] - n[idx + 2 * st]) * inv2h;
     if (i == N - 1) return (3.0 * n[idx] - 4.0 * n[idx - st] + n[idx - 2 * st]) * inv2h;
     return (n[idx + st] - n[idx - st]) * inv2h;
+}
+
+// Perdew-Wang 1992 correlation energy per electron of the unpolarised
+// uniform gas, eps_c(r_s) = -2A (1 + a1 r_s) ln(1 + 1/Q), Q = 2A (b1 r_s^1/2
+// + b2 r_s + b3 r_s^3/2 + b4 r_s^2), the logarithm as log1p; *dec = d eps_c / d r_s.
+__device__ inline double pw92_ec(double rs, double *dec)
+{
+    const double A = 0.031091, a1 = 0.21370;
+    const double b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+    double srs = sqrt(rs);
+    double Q = 2.0 * A * (srs * (b1 + b3 * rs) + rs * (b2 + b4 * rs));
+    double Lg = log1p(1.0 / Q);
+    if (dec) {
+        double dQ = 2.0 * A * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
+        *dec = -2.0 * A * a1 * Lg + 2.0 * A * (1.0 + a1 * rs) * dQ / (Q * (Q + 1.0));
+    }
+    return -2.0 * A * (1.0 + a1 * rs) * Lg;
 }
 
 // Point t (x fastest) of an nx x ny x nz grid of G points whose density
@@ -47,18 +65,12 @@ __device__ inline void grad_q0_point(const double *__restrict__ n, long t, int n
     double q = 0.0, a = 0.0, b = 0.0;
     if (nn >= n_cut) {
         const double pi = 3.14159265358979323846;
-        const double A = 0.031091, a1 = 0.21370;
-        const double b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
         const double Zab = -0.8491;
         double gg = gx * gx + gy * gy + gz * gz;
         double kF = cbrt(3.0 * pi * pi * nn);
         double rs = cbrt(3.0 / (4.0 * pi * nn));
-        double srs = sqrt(rs);
-        double Q = 2.0 * A * (srs * (b1 + b3 * rs) + rs * (b2 + b4 * rs));
-        double Lg = log1p(1.0 / Q);
-        double ec = -2.0 * A * (1.0 + a1 * rs) * Lg;
-        double dQ = 2.0 * A * (0.5 * b1 / srs + b2 + 1.5 * b3 * srs + 2.0 * b4 * rs);
-        double dec = -2.0 * A * a1 * Lg + 2.0 * A * (1.0 + a1 * rs) * dQ / (Q * (Q + 1.0));
+        double dec;
+        double ec = pw92_ec(rs, &dec);
         double inv_kn2 = 1.0 / (kF * nn * nn);
         q = kF - (4.0 * pi / 3.0) * ec - (Zab / 36.0) * gg * inv_kn2;
         a = kF / (3.0 * nn) + (4.0 * pi / 9.0) * dec * rs / nn + (7.0 * Zab / 108.0) * gg * inv_kn2 / nn;

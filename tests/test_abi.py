@@ -120,3 +120,43 @@ def test_batch_plan_host_validation(L):
                                       dummy) == L.VDW_EINVAL
     assert lib.enl_batch_plan_replay(None, None) == L.VDW_EINVAL
     assert lib.enl_batch_plan_destroy(None) == L.VDW_OK
+
+
+def test_xc_host_side(L, oracle):
+    """xc_energies rejects bad arguments before any device work; its
+    workspace grows with the grid up to a fixed number of block partials;
+    vdw_recombine (host arithmetic) is Eq. (3), checked against the oracle on
+    the paper's sample-run energies."""
+    import math
+
+    lib = L.lib()
+    g = L.VdwGrid()
+    g.n[:] = (8, 8, 8)
+    for a in range(3):
+        g.cell[a][a] = 8 * 0.4
+    small = lib.xc_workspace_size(ct.byref(g))
+    assert small > 0
+    g2 = L.VdwGrid()
+    g2.n[:] = (96, 96, 96)
+    for a in range(3):
+        g2.cell[a][a] = 96 * 0.25
+    big = lib.xc_workspace_size(ct.byref(g2))
+    assert small < big <= (5 * 2048 + 6) * 8
+    E = (ct.c_double * 5)()
+    ws = ct.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.xc_energies(ct.byref(g), None, 1e-12, ws, big, E, None) == L.VDW_EINVAL
+    assert lib.xc_energies(ct.byref(g), ws, -1.0, ws, big, E, None) == L.VDW_EINVAL
+    assert lib.xc_energies(ct.byref(g), ws, float("nan"), ws, big, E, None) == L.VDW_EINVAL
+    assert lib.xc_energies(ct.byref(g), ws, 1e-12, ws, small - 8, E, None) == L.VDW_EWORKSPACE
+    bad = L.VdwGrid()
+    bad.n[:] = (2, 8, 8)
+    assert lib.xc_workspace_size(ct.byref(bad)) == 0
+    # Eq. (3) on the sample run's printed energies (eV; only the differences matter)
+    ex_lda, ec_lda, ex_pbe, ec_pbe, ex_rev = -783.10552037, -59.77262220, -810.50311278, -42.20550892, -811.6072505786024
+    e_nl = 6.16752468
+    xc = (ct.c_double * 5)(ex_lda, ec_lda, ex_pbe, ec_pbe, ex_rev)
+    assert lib.vdw_recombine(xc, e_nl, 0.0, 0) == pytest.approx(oracle.recombine(e_nl, ec_lda, ec_pbe), abs=1e-12)
+    assert lib.vdw_recombine(xc, e_nl, -1234.5, 1) == pytest.approx(
+        oracle.recombine(e_nl, ec_lda, ec_pbe, Ex_pbe=ex_pbe, Ex_new=ex_rev, E_dft=-1234.5), abs=1e-9)
+    assert math.isnan(lib.vdw_recombine(xc, e_nl, 0.0, 2))
+    assert math.isnan(lib.vdw_recombine(None, e_nl, 0.0, 0))
