@@ -98,6 +98,10 @@ def lib():
         P(i32), P(i32), P(i32), dp, dp,
         dp, P(i32), P(i32), P(i32), d, dp, P(TableParams),
     ]
+    L.vo_pair_rows_cell.restype = ct.c_int
+    L.vo_pair_rows_cell.argtypes = L.vo_pair_rows.argtypes
+    L.vo_block_sum_cell.restype = d
+    L.vo_block_sum_cell.argtypes = L.vo_block_sum.argtypes
     L.vo_num_threads.restype = ct.c_int
     _lib = L
     return L
@@ -204,13 +208,17 @@ def self_phi(q, rho_s, tab, tp):
 
 
 # --------------------------------------------------------------------------
-# Grid (Sec. 2: equidistant grid; this path takes orthorhombic cells).
+# Grid (Sec. 2: the density on an equidistant grid of the unit cell; the
+# sample run of App. A has a hexagonal, i.e. skew, cell).
 # --------------------------------------------------------------------------
 
 
 @dataclass
 class Grid:
-    """Equidistant orthorhombic grid; point (ix, iy, iz) = (ix hx, iy hy, iz hz).
+    """Equidistant grid; point (ix, iy, iz) = ix e_x + iy e_y + iz e_z with the
+    step vectors e_a = (lattice vector a) / n_a.  Without `cell` the cell is
+    orthorhombic with e_a = h_a along axis a; with `cell` (rows: the lattice
+    vectors a, b, c in bohr) it may be skew, and `h` is not used.
 
     Arrays are (nz, ny, nx) in C order, so x is the fastest index.
     """
@@ -218,14 +226,43 @@ class Grid:
     n: tuple  # (nx, ny, nz)
     h: tuple  # (hx, hy, hz) bohr
     periodic: tuple = (0, 0, 0)
+    cell: tuple | None = None
 
     @property
     def G(self) -> int:
         return int(self.n[0] * self.n[1] * self.n[2])
 
     @property
+    def skew(self) -> bool:
+        if self.cell is None:
+            return False
+        c = np.asarray(self.cell, dtype=np.float64)
+        return bool(np.any(c[~np.eye(3, dtype=bool)] != 0.0))
+
+    @property
+    def steps(self) -> np.ndarray:
+        """3 x 3, row a = the step vector e_a."""
+        if self.cell is None:
+            return np.diag(np.asarray(self.h, dtype=np.float64))
+        c = np.asarray(self.cell, dtype=np.float64).reshape(3, 3)
+        return c / np.asarray(self.n, dtype=np.float64)[:, None]
+
+    @property
     def dV(self) -> float:
+        if self.skew:
+            return abs(float(np.linalg.det(self.steps)))
         return float(self.h[0] * self.h[1] * self.h[2])
+
+
+def grid_of_cell(n, cell, periodic=(0, 0, 0)) -> Grid:
+    """Grid of an n[0] x n[1] x n[2] division of the cell (rows a, b, c); a
+    diagonal cell gives the orthorhombic form."""
+    c = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    h = tuple(float(np.linalg.norm(c[a]) / n[a]) for a in range(3))
+    g = Grid(tuple(n), h, tuple(periodic), tuple(map(tuple, c)))
+    if not g.skew:
+        return Grid(tuple(n), tuple(float(c[a, a] / n[a]) for a in range(3)), tuple(periodic))
+    return g
 
 
 def cell_volume_element(cell, n) -> float:
@@ -266,9 +303,17 @@ def diff_matrix_1d(N: int, h: float, periodic: bool) -> sp.csr_matrix:
 
 
 def gradient_operators(grid: Grid):
-    """Sparse G x G operators (Gx, Gy, Gz) on the flattened (x fastest) grid."""
+    """Sparse G x G operators (Gx, Gy, Gz) on the flattened (x fastest) grid.
+    On a skew grid the differences along the grid axes give d_a = e_a . grad n
+    (per grid step), and grad n = E^-1 d with E the matrix of step vectors."""
     nx, ny, nz = grid.n
     Ix, Iy, Iz = sp.identity(nx), sp.identity(ny), sp.identity(nz)
+    if grid.skew:
+        D = (sp.kron(Iz, sp.kron(Iy, diff_matrix_1d(nx, 1.0, bool(grid.periodic[0])))).tocsr(),
+             sp.kron(Iz, sp.kron(diff_matrix_1d(ny, 1.0, bool(grid.periodic[1])), Ix)).tocsr(),
+             sp.kron(diff_matrix_1d(nz, 1.0, bool(grid.periodic[2])), sp.kron(Iy, Ix)).tocsr())
+        Einv = np.linalg.inv(grid.steps)
+        return tuple((Einv[c, 0] * D[0] + Einv[c, 1] * D[1] + Einv[c, 2] * D[2]).tocsr() for c in range(3))
     Dx = diff_matrix_1d(nx, grid.h[0], bool(grid.periodic[0]))
     Dy = diff_matrix_1d(ny, grid.h[1], bool(grid.periodic[1]))
     Dz = diff_matrix_1d(nz, grid.h[2], bool(grid.periodic[2]))
@@ -453,7 +498,9 @@ def pair_rows(grid: Grid, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), r_cut=
     S0c = np.zeros(nrows)
     S0i = np.zeros(nrows)
     Sq = np.zeros(nrows)
-    lib().vo_pair_rows(
+    if grid.skew:
+        h = np.ascontiguousarray(grid.steps.ravel())
+    (lib().vo_pair_rows_cell if grid.skew else lib().vo_pair_rows)(
         len(n), _p(ix, ct.c_int32), _p(iy, ct.c_int32), _p(iz, ct.c_int32), _p(n, ct.c_double), _p(q, ct.c_double),
         _p(h, ct.c_double), _p(gd, ct.c_int32), _p(per, ct.c_int32), _p(im, ct.c_int32), float(r_cut),
         _p(tab, ct.c_double), ct.byref(tp), nrows, rows_p, _p(S0c, ct.c_double), _p(S0i, ct.c_double), _p(Sq, ct.c_double),
@@ -475,7 +522,9 @@ def block_sum(grid: Grid, A, B, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), 
     gd = np.asarray(grid.n, dtype=np.int32)
     per = np.asarray(grid.periodic, dtype=np.int32)
     im = np.asarray(image_max, dtype=np.int32)
-    return float(lib().vo_block_sum(
+    if grid.skew:
+        h = np.ascontiguousarray(grid.steps.ravel())
+    return float((lib().vo_block_sum_cell if grid.skew else lib().vo_block_sum)(
         len(A), _p(A, ct.c_int32), len(B), _p(B, ct.c_int32),
         _p(ix, ct.c_int32), _p(iy, ct.c_int32), _p(iz, ct.c_int32), _p(n, ct.c_double), _p(q, ct.c_double),
         _p(h, ct.c_double), _p(gd, ct.c_int32), _p(per, ct.c_int32), _p(im, ct.c_int32), float(r_cut),

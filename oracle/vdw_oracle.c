@@ -436,6 +436,96 @@ double vo_block_sum(long na, const int32_t *ia, long nb, const int32_t *ib,
     return total;
 }
 
+/* ------------------------------------------------------------------ */
+/* The same two sums on a general (possibly skew) grid: point (i0,i1,i2)  */
+/* sits at r = i0 e_0 + i1 e_1 + i2 e_2 with the step vectors e_a as rows */
+/* of E (e_a = lattice vector a / n_a), and image L = sum_a m_a n_a e_a.   */
+/* The separation is formed in grid units first, then mapped by E.        */
+/* ------------------------------------------------------------------ */
+static double vo_cell_dist(const double E[9], double d0, double d1, double d2)
+{
+    double x = d0 * E[0] + d1 * E[3] + d2 * E[6];
+    double y = d0 * E[1] + d1 * E[4] + d2 * E[7];
+    double z = d0 * E[2] + d1 * E[5] + d2 * E[8];
+    return sqrt(x * x + y * y + z * z);
+}
+
+int vo_pair_rows_cell(long npts, const int32_t *ix, const int32_t *iy, const int32_t *iz,
+                      const double *n, const double *q,
+                      const double E[9], const int32_t gdim[3], const int32_t periodic[3],
+                      const int32_t image_max[3], double r_cut,
+                      const double *tab, const vo_table_params *p,
+                      long nrows, const int64_t *rows,
+                      double *S0_cell, double *S0_img, double *Sq)
+{
+    int mx = periodic[0] ? image_max[0] : 0;
+    int my = periodic[1] ? image_max[1] : 0;
+    int mz = periodic[2] ? image_max[2] : 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long t = 0; t < nrows; ++t) {
+        long i = rows ? (long)rows[t] : t;
+        double sc = 0.0, si = 0.0, sq = 0.0;
+        for (int a = -mx; a <= mx; ++a)
+            for (int b = -my; b <= my; ++b)
+                for (int c = -mz; c <= mz; ++c) {
+                    int home = (a == 0 && b == 0 && c == 0);
+                    for (long j = 0; j < npts; ++j) {
+                        if (home && j == i) continue;
+                        double r = vo_cell_dist(E, (double)(ix[i] - ix[j]) - (double)a * gdim[0],
+                                                (double)(iy[i] - iy[j]) - (double)b * gdim[1],
+                                                (double)(iz[i] - iz[j]) - (double)c * gdim[2]);
+                        if (r_cut > 0.0 && r > r_cut) continue;
+                        double dq;
+                        double ph = vo_pair_phi(q[i], q[j], r, tab, p, &dq);
+                        if (home) sc += n[j] * ph;
+                        else si += n[j] * ph;
+                        sq += n[j] * dq;
+                    }
+                }
+        S0_cell[t] = sc;
+        S0_img[t] = si;
+        Sq[t] = sq;
+    }
+    return 0;
+}
+
+double vo_block_sum_cell(long na, const int32_t *ia, long nb, const int32_t *ib,
+                         const int32_t *ix, const int32_t *iy, const int32_t *iz,
+                         const double *n, const double *q,
+                         const double E[9], const int32_t gdim[3], const int32_t periodic[3],
+                         const int32_t image_max[3], double r_cut,
+                         const double *tab, const vo_table_params *p)
+{
+    int mx = periodic[0] ? image_max[0] : 0;
+    int my = periodic[1] ? image_max[1] : 0;
+    int mz = periodic[2] ? image_max[2] : 0;
+    double *part = (double *)malloc(sizeof(double) * (size_t)(na > 0 ? na : 1));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long s = 0; s < na; ++s) {
+        long i = ia[s];
+        double acc = 0.0;
+        for (int a = -mx; a <= mx; ++a)
+            for (int b = -my; b <= my; ++b)
+                for (int c = -mz; c <= mz; ++c) {
+                    int home = (a == 0 && b == 0 && c == 0);
+                    for (long u = 0; u < nb; ++u) {
+                        long j = ib[u];
+                        if (home && j == i) continue;
+                        double r = vo_cell_dist(E, (double)(ix[i] - ix[j]) - (double)a * gdim[0],
+                                                (double)(iy[i] - iy[j]) - (double)b * gdim[1],
+                                                (double)(iz[i] - iz[j]) - (double)c * gdim[2]);
+                        if (r_cut > 0.0 && r > r_cut) continue;
+                        acc += n[i] * n[j] * vo_pair_phi(q[i], q[j], r, tab, p, NULL);
+                    }
+                }
+        part[s] = acc;
+    }
+    double total = 0.0;
+    for (long s = 0; s < na; ++s) total += part[s];
+    free(part);
+    return total;
+}
+
 int vo_num_threads(void)
 {
 #ifdef _OPENMP

@@ -32,6 +32,7 @@ class Workload:
     r_cut: float = 0.0
     table: dict = field(default_factory=lambda: dict(n_D=2048, n_sigma=64, D_max=48.0))
     meta: dict = field(default_factory=dict)
+    cell: tuple | None = None  # rows: lattice vectors a, b, c (bohr) of a skew cell; None: orthorhombic from h
 
     @property
     def G(self) -> int:
@@ -39,6 +40,8 @@ class Workload:
 
     @property
     def dV(self) -> float:
+        if self.cell is not None:
+            return abs(float(np.linalg.det(np.asarray(self.cell, dtype=np.float64)))) / self.G
         return float(self.h[0] * self.h[1] * self.h[2])
 
     def electrons(self) -> float:
@@ -75,6 +78,33 @@ def atom_density(n, h, center, Z, alphas, fracs, lateral_images=0, cell=None) ->
         r = np.sqrt(dz2 + dy2 + dx2)
         for A, a in zip(amps, alphas):
             out += A * np.exp(-a * r)
+    return out
+
+
+def cell_points(n, cell) -> np.ndarray:
+    """Cartesian positions (nz, ny, nx, 3) of the grid points
+    i0 e_0 + i1 e_1 + i2 e_2, e_a = cell[a] / n[a]."""
+    E = np.asarray(cell, dtype=np.float64) / np.asarray(n, dtype=np.float64)[:, None]
+    u2, u1, u0 = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    return u0[..., None] * E[0] + u1[..., None] * E[1] + u2[..., None] * E[2]
+
+
+def cell_atom_density(n, cell, center, Z, alphas, fracs, periodic=(0, 0, 0), images=0) -> np.ndarray:
+    """Exponential-shell atom on the grid of a (possibly skew) cell, repeated
+    over the lattice translations sum_a m_a cell[a] with |m_a| <= images on
+    periodic axes."""
+    P = cell_points(n, cell)
+    C = np.asarray(cell, dtype=np.float64)
+    out = np.zeros(P.shape[:3])
+    amps = [f * Z * a ** 3 / (8.0 * math.pi) for f, a in zip(fracs, alphas)]
+    rng_ = [range(-images, images + 1) if periodic[a] else range(0, 1) for a in range(3)]
+    for m0 in rng_[0]:
+        for m1 in rng_[1]:
+            for m2 in rng_[2]:
+                shift = m0 * C[0] + m1 * C[1] + m2 * C[2]
+                r = np.linalg.norm(P - (np.asarray(center) + shift), axis=-1)
+                for A, a in zip(amps, alphas):
+                    out += A * np.exp(-a * r)
     return out
 
 
@@ -130,6 +160,49 @@ def xe_slab(seed: int = 3, nxy: int = 48, nz: int = 224) -> Workload:
     rho = atom_density(n, h, (4.3, 4.3, 20.0), 54.0, KR_ALPHAS, f, lateral_images=4, cell=cell)
     return Workload(f"xe-slab-{nxy}x{nxy}x{nz}", n, h, (1, 1, 0), rho, 1e-5, image_max=(3, 3, 0), r_cut=30.0,
                     table=dict(n_D=2048, n_sigma=64, D_max=48.0), meta=dict(seed=seed, fracs=f.tolist(), cell=cell))
+
+
+HEX_CELL_XE = ((8.6, 0.0, 0.0), (4.3, 8.6 * math.sqrt(3.0) / 2.0, 0.0), (0.0, 0.0, 40.0))
+
+
+def xe_hex_slab(seed: int = 3, nxy: int = 48, nz: int = 224) -> Workload:
+    """The Xe-slab workload on the hexagonal cell of a close-packed monolayer
+    (the geometry of the paper's sample run, App. A): a = (8.6, 0, 0),
+    b = (4.3, 7.45, 0), c = (0, 0, 40) bohr, nxy x nxy x nz grid, periodic in
+    a and b, one 54-electron atom (alpha = 30, 8, 2.5, 0.8) at the cell centre
+    in the plane z = 20, periodised over |m|, |p| <= 4 cells; n_cut = 1e-5;
+    images |m|, |p| <= 4 with |r - r'| <= 30 bohr (the cell is thinner across
+    its short diagonal, so one more image ring than the square cell)."""
+    rng = np.random.default_rng(seed)
+    f = shell_weights(rng, 4)
+    n = (nxy, nxy, nz)
+    C = np.asarray(HEX_CELL_XE)
+    center = tuple(0.5 * C[0] + 0.5 * C[1] + np.array([0.0, 0.0, 20.0]))
+    rho = cell_atom_density(n, C, center, 54.0, KR_ALPHAS, f, periodic=(1, 1, 0), images=4)
+    h = tuple(float(np.linalg.norm(C[a]) / n[a]) for a in range(3))
+    return Workload(f"xe-hex-slab-{nxy}x{nxy}x{nz}", n, h, (1, 1, 0), rho, 1e-5, image_max=(4, 4, 0), r_cut=30.0,
+                    table=dict(n_D=2048, n_sigma=64, D_max=48.0), meta=dict(seed=seed, fracs=f.tolist()),
+                    cell=tuple(map(tuple, C)))
+
+
+def random_skew(n=(7, 6, 5), cell=((2.8, 0.0, 0.0), (1.1, 2.6, 0.0), (0.4, -0.3, 2.9)), periodic=(0, 0, 0),
+                seed: int = 0, n_cut: float = 1e-3, image_max=(0, 0, 0), r_cut: float = 0.0, table=None) -> Workload:
+    """A smooth random density on a small skew grid (three exponential blobs
+    at random fractional positions, repeated over one ring of cells on
+    periodic axes, plus a floor), for oracle pins and GPU parity."""
+    rng = np.random.default_rng(seed)
+    C = np.asarray(cell, dtype=np.float64)
+    rho = np.full((n[2], n[1], n[0]), 2e-3)
+    for _ in range(3):
+        frac = rng.uniform(0.2, 0.8, size=3)
+        Z = rng.uniform(0.5, 3.0)
+        a = rng.uniform(0.8, 3.0)
+        rho += cell_atom_density(n, C, tuple(frac @ C), Z, (a,), (1.0,), periodic=periodic, images=1)
+    rho *= rng.uniform(0.9, 1.1, size=rho.shape)
+    h = tuple(float(np.linalg.norm(C[a]) / n[a]) for a in range(3))
+    return Workload(f"skew-{n[0]}x{n[1]}x{n[2]}-s{seed}", tuple(n), h, tuple(periodic), rho, n_cut,
+                    image_max=tuple(image_max), r_cut=r_cut, table=table or dict(n_D=256, n_sigma=16, D_max=24.0),
+                    meta=dict(seed=seed), cell=tuple(map(tuple, C)))
 
 
 def molecule_batch(count: int = 64, seed: int = 5, min_edge: int = 16, max_edge: int = 64) -> list:
