@@ -45,7 +45,7 @@ enum {
     VDW_EINVAL = -1,        /* bad argument: null pointer, size, parameter range  */
     VDW_ENOMEM = -2,        /* host allocation failed (batch plan object)         */
     VDW_EHIP = -3,          /* a HIP runtime call failed                          */
-    VDW_EUNSUPPORTED = -4,  /* valid but not implemented (skew cell with FD grad) */
+    VDW_EUNSUPPORTED = -4,  /* valid but not implemented (Kahan runs on a skew cell) */
     VDW_EWORKSPACE = -5,    /* workspace smaller than enl_workspace_size()        */
     VDW_ENONFINITE = -6     /* NaN or Inf found in the density                    */
 };
@@ -53,11 +53,14 @@ enum {
 enum { VDW_FP64 = 0, VDW_FP32C = 1 };
 
 /* Equidistant grid (Sec. 2).  cell[a] is the a-th cell vector (bohr); grid
- * point (i, j, k) sits at i cell[0]/n[0] + j cell[1]/n[1] + k cell[2]/n[2].
- * Only orthorhombic cells (cell[a][b] = 0 for a != b) are supported, because
- * the finite-difference gradient is defined for perpendicular axes (Sec. 3);
- * other cells give VDW_EUNSUPPORTED.  periodic[a] = 1 marks a periodic axis
- * (the input's perx/pery/perz, App. A).  Every n[a] must be >= 3. */
+ * point (i, j, k) sits at i e_0 + j e_1 + k e_2, e_a = cell[a] / n[a].  Any
+ * non-degenerate cell is accepted: orthorhombic (cell[a][b] = 0 for a != b,
+ * cell[a][a] > 0) or skew, like the hexagonal cell of the sample run
+ * (App. A).  On skew cells the finite differences are taken along the grid
+ * axes and mapped to Cartesian components by the inverse of the step
+ * matrix, and pair distances use the full metric e_a . e_b.  periodic[a] = 1
+ * marks a periodic axis (the input's perx/pery/perz, App. A); images are
+ * whole cell translations.  Every n[a] must be >= 3. */
 typedef struct {
     int32_t n[3];
     double  cell[3][3];
@@ -105,7 +108,9 @@ typedef struct {
                                no images, else 1024); 0: auto (256 when, with
                                every grid point kept, the 1024-thread work
                                list at 1024-point chunks has fewer than 128
-                               items and there are no images; else 1024)     */
+                               items and there are no images; else 1024).
+                               Skew cells: always 1024 threads with blocks
+                               of 2048.                                       */
     int32_t j_chunks;       /* j-points per off-diagonal work item, in units of
                                1024 (1..64); 0: auto (the longest of 8, 4, 2,
                                1 whose work list, with every grid point kept,
@@ -113,7 +118,8 @@ typedef struct {
                                shorter than a row block split its diagonal
                                work into (block / chunk) items.               */
     int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
-    int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only)     */
+    int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only;
+                               not on skew cells)                             */
 } vdw_opts;
 
 /* Thread-local description of the last error (never NULL). */
@@ -150,8 +156,8 @@ int build_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, voi
  *   q0_d:    device, G doubles (written).
  *   dq_dn_d: device, G doubles, or NULL: dq0/dn at fixed |grad n|^2.
  *   dq_dg_d: device, G doubles, or NULL: dq0/d(|grad n|^2).
- * Errors: VDW_EINVAL (null pointers, n_cut <= 0, n[a] < 3),
- * VDW_EUNSUPPORTED (non-orthorhombic cell), VDW_EHIP.
+ * Errors: VDW_EINVAL (null pointers, n_cut <= 0, n[a] < 3, degenerate
+ * cell), VDW_EHIP.
  * ------------------------------------------------------------------- */
 int compute_q0(const vdw_grid *grid, double n_cut, const double *n_d, double *grad_d, double *q0_d,
                double *dq_dn_d, double *dq_dg_d, void *stream);
@@ -177,7 +183,7 @@ int compute_q0(const vdw_grid *grid, double n_cut, const double *n_d, double *gr
  *   ws:      device workspace of xc_workspace_size(grid) bytes.
  *   E:       host, 5 doubles, written after `stream` has been synchronised.
  * Errors: VDW_EINVAL (null pointers, n_floor < 0 or not finite, bad grid),
- * VDW_EUNSUPPORTED (non-orthorhombic cell), VDW_EWORKSPACE, VDW_ENONFINITE
+ * VDW_EWORKSPACE, VDW_ENONFINITE
  * (an energy is not finite; E is still written), VDW_EHIP.
  * ------------------------------------------------------------------- */
 size_t xc_workspace_size(const vdw_grid *grid);
@@ -205,14 +211,16 @@ size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, cons
  *             rho_s = (3 dV / 4 pi)^(1/3) e^(-1/3)     (if opts->self_term)
  * L runs over the images selected by opts->image_max on periodic axes
  * (Sec. 3, periodic problems), and every (i, j, L) with a distance above
- * opts->r_cut (if > 0) is dropped.  dV = hx hy hz.
+ * opts->r_cut (if > 0) is dropped.  dV = |det(cell)| / G (hx hy hz on
+ * orthorhombic cells).
  *   n_d, q0_d: device, G doubles (q0 from compute_q0).
  *   phi_d:     device FP64 table (always required: the on-site term and the
  *              VDW_FP64 pair kernel read it).
  *   phi_f:     device FP32 table (required for VDW_FP32C, else ignored).
  *   ws, ws_bytes: device workspace of at least enl_workspace_size() bytes.
  *   E_out:     host, 3 doubles: {E_pair0, E_pairL, E_self} (Hartree).
- * Errors: VDW_EINVAL, VDW_EUNSUPPORTED, VDW_EWORKSPACE, VDW_EHIP.
+ * Errors: VDW_EINVAL, VDW_EUNSUPPORTED (kahan = 1 on a skew cell),
+ * VDW_EWORKSPACE, VDW_EHIP.
  * ------------------------------------------------------------------- */
 int enl_energy(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *phi_d,
                const float *phi_f, const vdw_table_params *tp, const vdw_opts *opts, void *ws,

@@ -36,11 +36,14 @@ class TableParams:
 
 @dataclass
 class Grid:
-    """Orthorhombic equidistant grid: n points per axis, spacing h (bohr); x fastest."""
+    """Equidistant grid, n points per axis, x fastest.  Orthorhombic with
+    spacing h (bohr), or, with `cell` (rows: lattice vectors a, b, c in bohr),
+    any (skew) cell divided into n[0] x n[1] x n[2] steps (h is then unused)."""
 
     n: tuple
-    h: tuple
+    h: tuple = (0.0, 0.0, 0.0)
     periodic: tuple = (0, 0, 0)
+    cell: tuple | None = None
 
     @property
     def G(self) -> int:
@@ -48,6 +51,10 @@ class Grid:
 
     @property
     def dV(self) -> float:
+        if self.cell is not None:
+            import numpy as np
+
+            return abs(float(np.linalg.det(np.asarray(self.cell, dtype=np.float64)))) / self.G
         return float(self.h[0]) * float(self.h[1]) * float(self.h[2])
 
     def c(self) -> L.VdwGrid:
@@ -56,7 +63,10 @@ class Grid:
             g.n[a] = int(self.n[a])
             g.periodic[a] = int(self.periodic[a])
             for b in range(3):
-                g.cell[a][b] = float(self.n[a] * self.h[a]) if a == b else 0.0
+                if self.cell is not None:
+                    g.cell[a][b] = float(self.cell[a][b])
+                else:
+                    g.cell[a][b] = float(self.n[a] * self.h[a]) if a == b else 0.0
         return g
 
 

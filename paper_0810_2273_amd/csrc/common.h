@@ -9,12 +9,18 @@
 
 namespace vdw {
 
-// Orthorhombic grid as the kernels see it.
+// Grid as the kernels see it.  Point (ix, iy, iz) sits at ix e_x + iy e_y +
+// iz e_z, e_a = (lattice vector a) / n_a.  Orthorhombic cells (skew = 0)
+// use h_a = |e_a| alone; skew cells also carry the step matrix E (rows e_a)
+// and its inverse (grad n = E^-1 d, d_a the difference per grid step).
 struct GridDev {
     int32_t nx, ny, nz;
     int32_t px, py, pz;  // periodic flags
-    double hx, hy, hz;
+    double hx, hy, hz;   // |e_x|, |e_y|, |e_z|
     int64_t G;
+    int32_t skew;
+    double E[9], Einv[9];  // row-major; E[3a + c] = component c of e_a
+    double dV;             // |det E|
 };
 
 // Set the thread-local error message and return `code`.

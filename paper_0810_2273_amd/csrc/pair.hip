@@ -65,7 +65,11 @@ enum { HDR_ITEMS = 0, HDR_NTOTAL = 1, HDR_BLKS = 2, HDR_WORDS = 8 };
 struct Seg {
     // filled on the host
     int32_t nx, ny, nz, px, py, pz;
-    double hx, hy, hz, dV;
+    double hx, hy, hz, dV;  // |e_a| (the unit of the kernel's distances is h_x = |e_x|), cell volume / G
+    int32_t skew, pad1;
+    double einv[9];     // E^-1 (skew cells; gradient and its adjoint)
+    double m01, m02, m12;  // skew: 2 e_x.e_y / h_x^2, 2 e_x.e_z / h_x^2, 2 e_y.e_z / h_x^2
+    double lmin, lmax;     // skew: extreme eigenvalues of the metric e_a.e_b / h_x^2
     int64_t G, grid_off;
     int32_t nbx, nby, nbz, pad0;
     int64_t t_off, T;     // brick-order positions: offset (multiple of kCompactBlock), padded length
@@ -361,8 +365,13 @@ __device__ inline double wrot(double x)
 template <typename R>
 struct PairK {
     R tDmax, tDlds, tSclamp, csig, c4, casym, wy, wz;
+    R m01, m02, m12, lmin, lmax;  // skew cells (see Seg)
     int S, nS, K;
 };
+
+// Grid geometry of a pair-kernel variant: orthorhombic, cubic (equal
+// spacings), or skew (general metric).
+constexpr int kOrtho = 0, kCubic = 1, kSkew = 2;
 
 // min of two non-negative values; for FP32 an integer min on the bit
 // patterns (same order for non-negative floats, no NaN quieting needed)
@@ -373,11 +382,13 @@ __device__ inline float dmin(float a, float b)
 __device__ inline double dmin(double a, double b) { return __builtin_fmin(a, b); }
 
 // Squared distance in units of h_x^2 from exact integer grid deltas
-// (wy = (h_y/h_x)^2, wz = (h_z/h_x)^2; both 1 on cubic grids).
-template <typename R, bool CUBIC>
+// (wy = (h_y/h_x)^2, wz = (h_z/h_x)^2; both 1 on cubic grids; on skew grids
+// |e_a|^2 / h_x^2 and the cross terms m01 = 2 e_x.e_y / h_x^2, ...).
+template <typename R, int GEO>
 __device__ __forceinline__ R dist2(const PairK<R> &k, R dx, R dy, R dz)
 {
-    if (CUBIC) return dx * dx + dy * dy + dz * dz;
+    if (GEO == kCubic) return dx * dx + dy * dy + dz * dz;
+    if (GEO == kSkew) return dx * dx + (k.wy * dy) * dy + (k.wz * dz) * dz + dx * (k.m01 * dy + k.m02 * dz) + (k.m12 * dy) * dz;
     return dx * dx + (k.wy * dy) * dy + (k.wz * dz) * dz;
 }
 
@@ -535,13 +546,13 @@ __device__ __forceinline__ void kadd(R &sum, R &c, R y)
 // pair by pair (only for tiles that straddle it).  NORM (FP32 on cubic
 // grids) takes the squared distance from the exact integer form of dist2n,
 // with |x_j|^2 rotating along.
-template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, bool CUBIC, int IPL>
+template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, int GEO, int IPL>
 __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm,
                                        const R (&sx)[IPL], const R (&sy)[IPL], const R (&sz)[IPL], const R (&ai)[IPL],
                                        const R (&ci)[IPL], const R (&ni)[IPL], R xj, R yj, R zj, R wj, R aj, R nj,
                                        R (&acc)[IPL], R (&accq)[IPL], R &accj, R &accqj)
 {
-    constexpr bool NORM = CUBIC && sizeof(R) == 4;
+    constexpr bool NORM = GEO == kCubic && sizeof(R) == 4;
     R mx[IPL], my[IPL], mz[IPL], wi[IPL], ca[IPL], cq[IPL];
 #pragma unroll
     for (int p = 0; p < IPL; ++p) {
@@ -563,7 +574,7 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
                 m = (R)dist2n((float)mx[p], (float)my[p], (float)mz[p], (float)(wi[p] + wj), (float)xj, (float)yj,
                               (float)zj);
             else
-                m = dist2<R, CUBIC>(kc, sx[p] - xj, sy[p] - yj, sz[p] - zj);
+                m = dist2<R, GEO>(kc, sx[p] - xj, sy[p] - yj, sz[p] - zj);
             R ph, q = 0, jq = 0;
             pair_eval<ADJ, true, NSIG>(kc, tab, tabg, m, ai[p], ci[p], aj, cj_, ph, q, jq);
             R wjp = nj, wip = ni[p];
@@ -646,12 +657,14 @@ __device__ inline double uniform(double v)
 }
 
 // Smallest and largest squared distance (units of h_x^2) between two boxes
-// whose x, y, z ranges are given, after shifting the second by (sx, sy, sz).
-template <typename R>
-__device__ inline void box_dist2(const R *bi, const R *bj, R sx, R sy, R sz, R wy, R wz, R &dmin2, R &dmax2)
+// whose grid-index ranges are given, after shifting the second by
+// (sx, sy, sz).  On skew grids the metric is bounded by its extreme
+// eigenvalues, which gives a lower and an upper bound.
+template <typename R, bool SKEW>
+__device__ inline void box_dist2(const PairK<R> &k, const R *bi, const R *bj, R sx, R sy, R sz, R &dmin2, R &dmax2)
 {
     const R sh[3] = {sx, sy, sz};
-    const R wt[3] = {(R)1, wy, wz};
+    const R wt[3] = {(R)1, SKEW ? (R)1 : k.wy, SKEW ? (R)1 : k.wz};
     dmin2 = 0;
     dmax2 = 0;
     for (int a = 0; a < 3; ++a) {
@@ -662,12 +675,16 @@ __device__ inline void box_dist2(const R *bi, const R *bj, R sx, R sy, R sz, R w
         dmin2 += wt[a] * gap * gap;
         dmax2 += wt[a] * far * far;
     }
+    if (SKEW) {
+        dmin2 *= k.lmin;
+        dmax2 *= k.lmax;
+    }
 }
 
 // Pointers are separate __restrict__ parameters so the compiler knows the
 // records, segments and table are not written during the kernel and can
 // fetch wave-uniform records with scalar loads.
-template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL, int TPB>
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, int GEO, int IPL, int TPB>
 __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename RecOf<R>::T *__restrict__ recs,
                                                             const Seg *__restrict__ segs,
                                                             const int64_t *__restrict__ hdr, int *__restrict__ counter,
@@ -677,7 +694,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
 {
     using Rec = typename RecOf<R>::T;
     constexpr int NJc = 1 + (IMG ? 1 : 0) + (ADJ ? 1 : 0);
-    constexpr bool NORM = CUBIC && sizeof(R) == 4;
+    constexpr bool NORM = GEO == kCubic && sizeof(R) == 4;
     // static LDS: the table rows (K x S, row stride S = n_sigma + 1), the
     // j-side sums of one tile from every wavefront, the work-item slot
     constexpr int NW = TPB / 64;  // wavefronts of the workgroup
@@ -737,6 +754,13 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
         const int64_t slot = sg.slot_base + local;
         kc.wy = (R)((sg.hy / sg.hx) * (sg.hy / sg.hx));
         kc.wz = (R)((sg.hz / sg.hx) * (sg.hz / sg.hx));
+        if (GEO == kSkew) {
+            kc.m01 = (R)sg.m01;
+            kc.m02 = (R)sg.m02;
+            kc.m12 = (R)sg.m12;
+            kc.lmin = (R)sg.lmin;
+            kc.lmax = (R)sg.lmax;
+        }
         const R rcm = (R)(A.rc2 / (sg.hx * sg.hx));  // distance cut in units of h_x^2
         const Rec *__restrict__ P = recs + sg.p_off;
 
@@ -801,7 +825,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                                 m = (R)dist2n((float)mx[p], (float)my[p], (float)mz[p], (float)(wi[p] + J.w),
                                               (float)J.x, (float)J.y, (float)J.z);
                             else
-                                m = dist2<R, CUBIC>(kc, sx[p] - J.x, sy[p] - J.y, sz[p] - J.z);
+                                m = dist2<R, GEO>(kc, sx[p] - J.x, sy[p] - J.y, sz[p] - J.z);
                             R wt = (m > (R)0) ? J.n : (R)0;
                             if (IMG) wt = (m <= rcm) ? wt : (R)0;
                             R ph, q = 0, unused;
@@ -871,7 +895,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                         if (prune) {
                             // r_i - r_j - L: the j box shifted by +L against the i box
                             R dmin2, dmax2;
-                            box_dist2<R>(ib, jb6, lx, ly, lz, kc.wy, kc.wz, dmin2, dmax2);
+                            box_dist2<R, GEO == kSkew>(kc, ib, jb6, lx, ly, lz, dmin2, dmax2);
                             if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
                             masked = dmax2 > rcm;
                         }
@@ -887,11 +911,11 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                     R accj = 0, accqj = 0;
                     const R nj0 = jv ? Jr.n : (R)0;
                     if (masked)
-                        ring64<R, ADJ, true, KAHAN, NSIG, CUBIC, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
+                        ring64<R, ADJ, true, KAHAN, NSIG, GEO, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
                                                                       Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
                                                                       accqj);
                     else
-                        ring64<R, ADJ, false, KAHAN, NSIG, CUBIC, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
+                        ring64<R, ADJ, false, KAHAN, NSIG, GEO, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
                                                                        Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
                                                                        accqj);
 #pragma unroll
@@ -1094,12 +1118,24 @@ struct AsmArgs {
     double *dEdn;
 };
 
+// B_a at grid point gl: dE/dq dq/dg 2 (grad n)_a on orthorhombic grids; on
+// skew grids the same Cartesian vector mapped back to the grid axes by the
+// transpose of E^-1 (the derivative with respect to the difference d_a).
+template <bool SKEW>
 __device__ inline double bval(const AsmArgs &A, const Seg &s, int axis, int64_t gl)
 {
     int64_t g = s.grid_off + gl;
-    return A.dEdq[g] * A.dqdg[g] * 2.0 * A.grad[3 * s.grid_off + axis * s.G + gl];
+    const double *gr = A.grad + 3 * s.grid_off + gl;
+    if (SKEW)
+        return A.dEdq[g] * A.dqdg[g] * 2.0 *
+               (s.einv[axis] * gr[0] + s.einv[3 + axis] * gr[s.G] + s.einv[6 + axis] * gr[2 * s.G]);
+    return A.dEdq[g] * A.dqdg[g] * 2.0 * gr[axis * s.G];
 }
 
+// Transposed difference stencil of axis `axis` applied to B at point idx
+// (index k of N along the axis, stride st); h = 1 on skew grids (differences
+// per grid step).
+template <bool SKEW>
 __device__ inline double tstencil(const AsmArgs &A, const Seg &s, int axis, int64_t idx, int k, int N, int64_t st,
                                   int per, double h)
 {
@@ -1107,20 +1143,20 @@ __device__ inline double tstencil(const AsmArgs &A, const Seg &s, int axis, int6
     if (per) {
         int64_t up = (k + 1 == N) ? -(int64_t)(N - 1) * st : st;
         int64_t dn = (k == 0) ? (int64_t)(N - 1) * st : -st;
-        acc = bval(A, s, axis, idx + dn) - bval(A, s, axis, idx + up);
+        acc = bval<SKEW>(A, s, axis, idx + dn) - bval<SKEW>(A, s, axis, idx + up);
     } else {
         // interior rows i = k-1 (coefficient +1 at k) and i = k+1 (coefficient -1 at k)
-        if (k - 1 >= 1 && k - 1 <= N - 2) acc += bval(A, s, axis, idx - st);
-        if (k + 1 >= 1 && k + 1 <= N - 2) acc -= bval(A, s, axis, idx + st);
+        if (k - 1 >= 1 && k - 1 <= N - 2) acc += bval<SKEW>(A, s, axis, idx - st);
+        if (k + 1 >= 1 && k + 1 <= N - 2) acc -= bval<SKEW>(A, s, axis, idx + st);
         // face row i = 0: (-3, 4, -1) on (0, 1, 2)
         if (k <= 2) {
             const double c0[3] = {-3.0, 4.0, -1.0};
-            acc += c0[k] * bval(A, s, axis, idx - (int64_t)k * st);
+            acc += c0[k] * bval<SKEW>(A, s, axis, idx - (int64_t)k * st);
         }
         // face row i = N-1: (1, -4, 3) on (N-3, N-2, N-1)
         if (k >= N - 3) {
             const double c1[3] = {1.0, -4.0, 3.0};
-            acc += c1[k - (N - 3)] * bval(A, s, axis, idx + (int64_t)(N - 1 - k) * st);
+            acc += c1[k - (N - 3)] * bval<SKEW>(A, s, axis, idx + (int64_t)(N - 1 - k) * st);
         }
     }
     return acc * (0.5 / h);
@@ -1137,9 +1173,16 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmArgs A)
     const int64_t r = gl / s.nx;
     const int iy = (int)(r % s.ny);
     const int iz = (int)(r / s.ny);
-    double v = tstencil(A, s, 0, gl, ix, s.nx, 1, s.px, s.hx);
-    v += tstencil(A, s, 1, gl, iy, s.ny, s.nx, s.py, s.hy);
-    v += tstencil(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, s.hz);
+    double v;
+    if (s.skew) {
+        v = tstencil<true>(A, s, 0, gl, ix, s.nx, 1, s.px, 1.0);
+        v += tstencil<true>(A, s, 1, gl, iy, s.ny, s.nx, s.py, 1.0);
+        v += tstencil<true>(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, 1.0);
+    } else {
+        v = tstencil<false>(A, s, 0, gl, ix, s.nx, 1, s.px, s.hx);
+        v += tstencil<false>(A, s, 1, gl, iy, s.ny, s.nx, s.py, s.hy);
+        v += tstencil<false>(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, s.hz);
+    }
     A.dEdn[t] += v;
 }
 
@@ -1156,7 +1199,8 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
     if (t >= Gtot) return;
     const Seg &s = segs[find_seg(segs, B, t, 4)];
     const int64_t o = s.grid_off;
-    grad_q0_point(n + o, (long)(t - o), s.nx, s.ny, s.nz, s.px, s.py, s.pz, s.hx, s.hy, s.hz, (long)s.G, n_cut,
+    grad_q0_point(n + o, (long)(t - o), s.nx, s.ny, s.nz, s.px, s.py, s.pz, s.hx, s.hy, s.hz, s.skew ? s.einv : nullptr,
+                  (long)s.G, n_cut,
                   grad ? grad + 3 * o : nullptr, q0 + o, dqdn ? dqdn + o : nullptr, dqdg ? dqdg + o : nullptr);
 }
 
@@ -1177,6 +1221,7 @@ struct Plan {
     int nimg = 1, home = 0;
     int mimg[3] = {0, 0, 0};  // image range per axis (0 on open axes)
     bool img = false;
+    bool skew = false;  // some density has a skew cell: the general-metric kernels
     int JC = 8192;
     int tpb = kPairThreads;     // pair-kernel workgroup size
     int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
@@ -1213,6 +1258,33 @@ int64_t items_bound(int64_t G, int64_t BI, int64_t JC, int64_t ND)
 // when ND = BI / JC.
 int diag_items(int64_t BI, int64_t JC) { return BI > JC ? (int)(BI / JC) : 1; }
 
+// Bounds on the eigenvalues of a symmetric positive-definite 3 x 3 matrix
+// (trigonometric solution of the characteristic cubic, O. K. Smith, 1961),
+// widened by 1e-5 relative so the distance bounds built on them stay
+// conservative after rounding.
+void sym3_eig_bounds(const double M[3][3], double *lmin, double *lmax)
+{
+    const double p1 = M[0][1] * M[0][1] + M[0][2] * M[0][2] + M[1][2] * M[1][2];
+    const double q = (M[0][0] + M[1][1] + M[2][2]) / 3.0;
+    double e_min, e_max;
+    if (p1 == 0.0) {
+        e_min = fmin(M[0][0], fmin(M[1][1], M[2][2]));
+        e_max = fmax(M[0][0], fmax(M[1][1], M[2][2]));
+    } else {
+        const double d0 = M[0][0] - q, d1 = M[1][1] - q, d2 = M[2][2] - q;
+        const double p = sqrt((d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1) / 6.0);
+        const double B00 = d0 / p, B11 = d1 / p, B22 = d2 / p;
+        const double B01 = M[0][1] / p, B02 = M[0][2] / p, B12 = M[1][2] / p;
+        double r = 0.5 * (B00 * (B11 * B22 - B12 * B12) - B01 * (B01 * B22 - B12 * B02) + B02 * (B01 * B12 - B11 * B02));
+        r = fmin(1.0, fmax(-1.0, r));
+        const double phi = acos(r) / 3.0;
+        e_max = q + 2.0 * p * cos(phi);
+        e_min = q + 2.0 * p * cos(phi + 2.0 * 3.14159265358979323846 / 3.0);
+    }
+    *lmin = e_min * (1.0 - 1e-5);
+    *lmax = e_max * (1.0 + 1e-5);
+}
+
 // Compute units of the target (gfx950): the pair kernel runs one persistent
 // workgroup per CU, so the work list needs many more items than this to
 // keep every CU busy to the end.
@@ -1222,6 +1294,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
               Plan *P)
 {
     P->segs.resize(B);
+    P->skew = false;
     int64_t Gtot = 0;
     for (int b = 0; b < B; ++b) {
         GridDev g;
@@ -1240,7 +1313,22 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         s.hx = g.hx;
         s.hy = g.hy;
         s.hz = g.hz;
-        s.dV = g.hx * g.hy * g.hz;
+        s.dV = g.dV;
+        s.skew = g.skew;
+        for (int k = 0; k < 9; ++k) s.einv[k] = g.Einv[k];
+        {
+            // metric e_a.e_b / h_x^2 (diagonal on orthorhombic cells)
+            double M[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c)
+                    M[a][c] = (g.E[3 * a] * g.E[3 * c] + g.E[3 * a + 1] * g.E[3 * c + 1] + g.E[3 * a + 2] * g.E[3 * c + 2]) /
+                              (g.hx * g.hx);
+            s.m01 = 2.0 * M[0][1];
+            s.m02 = 2.0 * M[0][2];
+            s.m12 = 2.0 * M[1][2];
+            sym3_eig_bounds(M, &s.lmin, &s.lmax);
+        }
+        if (g.skew) P->skew = true;
         s.G = g.G;
         s.grid_off = grid_off ? grid_off[b] : 0;
         if (grid_off && grid_off[b + 1] - grid_off[b] != g.G)
@@ -1260,12 +1348,17 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             if (grids[0].periodic[a] && o->image_max[a] > 0) nimg *= 2 * o->image_max[a] + 1;
         const bool img = nimg > 1 || o->r_cut > 0.0;
         const bool fast = !fp64 && !o->kahan && nsig == 64;
+        if (P->skew && o->kahan) return fail(VDW_EUNSUPPORTED, "kahan = 1 is not available on skew cells");
         // workgroup shape: 512 threads with eight i-points per lane on request
         // (FP32 n_sigma = 64 kernels without images); 256 threads with two on
         // request or, by default, when even the finest chunking of the
-        // 1024-thread list leaves half the CUs idle (no images); else 1024
-        const int64_t BI_big = (int64_t)ipl_for(fp64, o->kahan, nsig, img) * kPairThreads;
-        if (fast && !img && o->block_threads == 512) {
+        // 1024-thread list leaves half the CUs idle (no images); else 1024.
+        // Skew cells: 1024 threads, two i-points per lane.
+        const int64_t BI_big = (int64_t)(P->skew ? 2 : ipl_for(fp64, o->kahan, nsig, img)) * kPairThreads;
+        if (P->skew) {
+            P->tpb = kPairThreads;
+            P->BI = (int)BI_big;
+        } else if (fast && !img && o->block_threads == 512) {
             P->tpb = 512;
             P->BI = 8 * 512;
         } else if (!img && (o->block_threads == 256 || (o->block_threads == 0 && bound(BI_big, 1024) < kCUs / 2))) {
@@ -1395,7 +1488,7 @@ struct PairPtrs {
     void *jpart;
 };
 
-template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, bool CUBIC, int IPL, int TPB>
+template <typename R, bool ADJ, bool IMG, bool KAHAN, int NSIG, int GEO, int IPL, int TPB>
 int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
     // the work layout was made for this row-block length
@@ -1403,7 +1496,7 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
         return fail(VDW_EINVAL, "internal: row blocks of %d points planned for a kernel with %d", a.BI, IPL * TPB);
     // the kernel's LDS is static (kLdsBytes); nothing else to set up
     if (attr_only) return VDW_OK;
-    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, CUBIC, IPL, TPB>), dim3(grid), dim3(TPB), lds, s, a,
+    hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, GEO, IPL, TPB>), dim3(grid), dim3(TPB), lds, s, a,
                        (const typename RecOf<R>::T *)p.recs, p.segs, p.hdr, p.counter, (const R *)p.tabg, p.imgs,
                        p.rowoff, p.ipart, (R *)p.jpart);
     VDW_HIP(hipGetLastError());
@@ -1416,43 +1509,58 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 // n_sigma, Kahan-compensated FP32C, and plain FP64 (two per lane, 1024
 // threads); each with and without the adjoint sums and the image loop.
 // Without images every one of them also has 256-thread workgroups with two
-// i-points per lane, for work lists too short to occupy every CU.
-template <typename R, bool KAHAN, int NSIG, bool CUBIC>
+// i-points per lane, for work lists too short to occupy every CU.  Skew
+// cells (FP64, FP32C with n_sigma = 64 or any) have two i-points per lane in
+// 1024-thread workgroups, with and without the adjoint and the image loop.
+template <typename R, bool KAHAN, int NSIG, int GEO>
 int launch_pair_v(int adj, int img, int tpb, const PairArgs &a, const PairPtrs &p, int grid, size_t lds,
                   hipStream_t s, bool attr_only)
 {
-    constexpr bool FAST = sizeof(R) == 4 && !KAHAN && NSIG == 64;
-    if (!img && tpb == 256)
-        return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, 2, 256>(a, p, grid, lds, s, attr_only)
-                   : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, 2, 256>(a, p, grid, lds, s, attr_only);
-    if (img) return adj ? launch_pair_t<R, true, true, KAHAN, NSIG, CUBIC, 2, 1024>(a, p, grid, lds, s, attr_only)
-                        : launch_pair_t<R, false, true, KAHAN, NSIG, CUBIC, 2, 1024>(a, p, grid, lds, s, attr_only);
-    if constexpr (FAST) {
-        if (tpb == 512)
-            return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only)
-                       : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, 8, 512>(a, p, grid, lds, s, attr_only);
+    if constexpr (GEO == kSkew) {
+        if (img) return adj ? launch_pair_t<R, true, true, KAHAN, NSIG, GEO, 2, 1024>(a, p, grid, lds, s, attr_only)
+                            : launch_pair_t<R, false, true, KAHAN, NSIG, GEO, 2, 1024>(a, p, grid, lds, s, attr_only);
+        return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, GEO, 2, 1024>(a, p, grid, lds, s, attr_only)
+                   : launch_pair_t<R, false, false, KAHAN, NSIG, GEO, 2, 1024>(a, p, grid, lds, s, attr_only);
+    } else {
+        constexpr bool FAST = sizeof(R) == 4 && !KAHAN && NSIG == 64;
+        if (!img && tpb == 256)
+            return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, GEO, 2, 256>(a, p, grid, lds, s, attr_only)
+                       : launch_pair_t<R, false, false, KAHAN, NSIG, GEO, 2, 256>(a, p, grid, lds, s, attr_only);
+        if (img) return adj ? launch_pair_t<R, true, true, KAHAN, NSIG, GEO, 2, 1024>(a, p, grid, lds, s, attr_only)
+                            : launch_pair_t<R, false, true, KAHAN, NSIG, GEO, 2, 1024>(a, p, grid, lds, s, attr_only);
+        if constexpr (FAST) {
+            if (tpb == 512)
+                return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, GEO, 8, 512>(a, p, grid, lds, s, attr_only)
+                           : launch_pair_t<R, false, false, KAHAN, NSIG, GEO, 8, 512>(a, p, grid, lds, s, attr_only);
+        }
+        constexpr int W = FAST ? 4 : 2;
+        return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, GEO, W, 1024>(a, p, grid, lds, s, attr_only)
+                   : launch_pair_t<R, false, false, KAHAN, NSIG, GEO, W, 1024>(a, p, grid, lds, s, attr_only);
     }
-    constexpr int W = FAST ? 4 : 2;
-    return adj ? launch_pair_t<R, true, false, KAHAN, NSIG, CUBIC, W, 1024>(a, p, grid, lds, s, attr_only)
-               : launch_pair_t<R, false, false, KAHAN, NSIG, CUBIC, W, 1024>(a, p, grid, lds, s, attr_only);
 }
 
-int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int cubic, int tpb, const PairArgs &a,
+int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tpb, const PairArgs &a,
                 const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
-    if (fp64) return launch_pair_v<double, false, 0, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
-    if (kahan) return launch_pair_v<float, true, 0, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (geo == kSkew) {
+        if (kahan) return fail(VDW_EUNSUPPORTED, "kahan = 1 is not available on skew cells");
+        if (fp64) return launch_pair_v<double, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        if (nsig == 64) return launch_pair_v<float, false, 64, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        return launch_pair_v<float, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    }
+    if (fp64) return launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (kahan) return launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (nsig == 64)
-        return cubic ? launch_pair_v<float, false, 64, true>(adj, img, tpb, a, p, grid, lds, s, attr_only)
-                     : launch_pair_v<float, false, 64, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
-    return launch_pair_v<float, false, 0, false>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        return geo == kCubic ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                             : launch_pair_v<float, false, 64, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    return launch_pair_v<float, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
 }
 
 // Everything an evaluation needs that does not depend on the data: the
 // work layout, the launch shapes and the constant kernel arguments.
 struct Exec {
     Plan P;
-    int B = 0, adj = 0, fp64 = 0, kahan = 0, nsig = 0, cubic = 1, self_term = 0;
+    int B = 0, adj = 0, fp64 = 0, kahan = 0, nsig = 0, geo = kCubic, self_term = 0;
     int tpb = 1024;  // pair-kernel workgroup size
     int K = 0, grid = 0;
     size_t lds = 0;
@@ -1536,18 +1644,20 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.jstride = P.L.slots * (int64_t)P.JC;
     // cubic grids take the exact integer form of the squared distance: its
     // partial sums stay below 12 c^2 for coordinates |c| <= c_max (image
-    // shifts included), exact in FP32 while 12 c_max^2 < 2^24
-    E->cubic = 1;
+    // shifts included), exact in FP32 while 12 c_max^2 < 2^24; skew cells
+    // take the general metric
+    E->geo = kCubic;
     double cmax = 0.0;
     for (int b = 0; b < B; ++b) {
         const Seg &g = P.segs[b];
-        if (!(g.hx == g.hy && g.hx == g.hz)) E->cubic = 0;
+        if (!(g.hx == g.hy && g.hx == g.hz)) E->geo = kOrtho;
         const int n3[3] = {g.nx, g.ny, g.nz};
         for (int a = 0; a < 3; ++a) cmax = fmax(cmax, (double)n3[a] * (1 + P.mimg[a]));
     }
-    if (12.0 * cmax * cmax >= 16777216.0) E->cubic = 0;
+    if (12.0 * cmax * cmax >= 16777216.0) E->geo = kOrtho;
+    if (P.skew) E->geo = kSkew;
     PairPtrs none{};
-    return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->cubic, E->tpb, pa, none, E->grid, E->lds, nullptr,
+    return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->geo, E->tpb, pa, none, E->grid, E->lds, nullptr,
                        true);
 }
 
@@ -1628,7 +1738,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     pp.ipart = ipart;
     pp.jpart = jpart;
     if (ev0) VDW_HIP(hipEventRecord(ev0, s));
-    int rc = launch_pair(E.fp64, E.adj, P.img ? 1 : 0, E.kahan, E.nsig, E.cubic, E.tpb, E.pa, pp, E.grid, E.lds, s,
+    int rc = launch_pair(E.fp64, E.adj, P.img ? 1 : 0, E.kahan, E.nsig, E.geo, E.tpb, E.pa, pp, E.grid, E.lds, s,
                          false);
     if (rc) return rc;
     if (ev1) VDW_HIP(hipEventRecord(ev1, s));

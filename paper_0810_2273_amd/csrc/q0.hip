@@ -1,6 +1,7 @@
 // Density gradient by second-order finite differences (the paper's Sec. 3
-// real-space option, perpendicular axes) and q0 of Dion et al. from the LDA
-// exchange, the Perdew-Wang 1992 correlation and the gradient term.
+// real-space option; along the grid axes, mapped to Cartesian components on
+// skew cells) and q0 of Dion et al. from the LDA exchange, the Perdew-Wang
+// 1992 correlation and the gradient term.
 // One thread per grid point, FP64 throughout.
 #include <math.h>
 
@@ -17,7 +18,8 @@ __global__ __launch_bounds__(256) void grad_q0_kernel(GridDev g, double n_cut, c
 {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= g.G) return;
-    grad_q0_point(n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.G, n_cut, grad, q0, dqdn, dqdg);
+    grad_q0_point(n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.skew ? g.Einv : nullptr, g.G, n_cut,
+                  grad, q0, dqdn, dqdg);
 }
 
 }  // namespace

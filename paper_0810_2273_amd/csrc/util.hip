@@ -22,19 +22,31 @@ int fail(int code, const char *fmt, ...)
 int validate_grid(const vdw_grid *g, GridDev *out)
 {
     if (!g) return fail(VDW_EINVAL, "grid is NULL");
+    int skew = 0;
     for (int a = 0; a < 3; ++a) {
         if (g->n[a] < 3) return fail(VDW_EINVAL, "grid n[%d] = %d < 3", a, g->n[a]);
         for (int b = 0; b < 3; ++b) {
             double v = g->cell[a][b];
             if (!isfinite(v)) return fail(VDW_EINVAL, "cell[%d][%d] is not finite", a, b);
-            if (a != b && v != 0.0)
-                return fail(VDW_EUNSUPPORTED,
-                            "non-orthorhombic cell (cell[%d][%d] = %g): the finite-difference "
-                            "gradient needs perpendicular axes", a, b, v);
+            if (a != b && v != 0.0) skew = 1;
         }
-        if (!(g->cell[a][a] > 0.0)) return fail(VDW_EINVAL, "cell[%d][%d] must be > 0", a, a);
         if (g->periodic[a] != 0 && g->periodic[a] != 1)
             return fail(VDW_EINVAL, "periodic[%d] must be 0 or 1", a);
+    }
+    double E[9];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) E[3 * a + c] = g->cell[a][c] / g->n[a];
+    // cofactors: Einv = adj(E) / det(E)
+    const double C00 = E[4] * E[8] - E[5] * E[7], C01 = E[5] * E[6] - E[3] * E[8], C02 = E[3] * E[7] - E[4] * E[6];
+    const double det = E[0] * C00 + E[1] * C01 + E[2] * C02;
+    if (!skew) {
+        for (int a = 0; a < 3; ++a)
+            if (!(g->cell[a][a] > 0.0)) return fail(VDW_EINVAL, "cell[%d][%d] must be > 0", a, a);
+    } else {
+        const double la = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+        const double lb = sqrt(E[3] * E[3] + E[4] * E[4] + E[5] * E[5]);
+        const double lc = sqrt(E[6] * E[6] + E[7] * E[7] + E[8] * E[8]);
+        if (!(fabs(det) > 1e-6 * la * lb * lc)) return fail(VDW_EINVAL, "degenerate cell (|det| = %g)", fabs(det));
     }
     int64_t G = (int64_t)g->n[0] * g->n[1] * g->n[2];
     if (G > (int64_t)1 << 31) return fail(VDW_EINVAL, "grid too large (%lld points)", (long long)G);
@@ -45,10 +57,34 @@ int validate_grid(const vdw_grid *g, GridDev *out)
         out->px = g->periodic[0];
         out->py = g->periodic[1];
         out->pz = g->periodic[2];
-        out->hx = g->cell[0][0] / g->n[0];
-        out->hy = g->cell[1][1] / g->n[1];
-        out->hz = g->cell[2][2] / g->n[2];
         out->G = G;
+        out->skew = skew;
+        for (int k = 0; k < 9; ++k) out->E[k] = E[k];
+        if (!skew) {
+            out->hx = g->cell[0][0] / g->n[0];
+            out->hy = g->cell[1][1] / g->n[1];
+            out->hz = g->cell[2][2] / g->n[2];
+            out->dV = out->hx * out->hy * out->hz;
+            for (int k = 0; k < 9; ++k) out->Einv[k] = 0.0;
+            out->Einv[0] = 1.0 / out->hx;
+            out->Einv[4] = 1.0 / out->hy;
+            out->Einv[8] = 1.0 / out->hz;
+        } else {
+            out->hx = sqrt(E[0] * E[0] + E[1] * E[1] + E[2] * E[2]);
+            out->hy = sqrt(E[3] * E[3] + E[4] * E[4] + E[5] * E[5]);
+            out->hz = sqrt(E[6] * E[6] + E[7] * E[7] + E[8] * E[8]);
+            out->dV = fabs(det);
+            const double id = 1.0 / det;
+            out->Einv[0] = C00 * id;
+            out->Einv[3] = C01 * id;
+            out->Einv[6] = C02 * id;
+            out->Einv[1] = (E[2] * E[7] - E[1] * E[8]) * id;
+            out->Einv[4] = (E[0] * E[8] - E[2] * E[6]) * id;
+            out->Einv[7] = (E[1] * E[6] - E[0] * E[7]) * id;
+            out->Einv[2] = (E[1] * E[5] - E[2] * E[4]) * id;
+            out->Einv[5] = (E[2] * E[3] - E[0] * E[5]) * id;
+            out->Einv[8] = (E[0] * E[4] - E[1] * E[3]) * id;
+        }
     }
     return VDW_OK;
 }

@@ -45,13 +45,18 @@ __device__ inline void xc_point(const XcArgs &a, int64_t t, double e[kXcTerms])
     // (3 pi^2)^(1/3) and (3 / (4 pi))^(1/3): k_F and r_s from one cube root
     const double c_kf = 3.0936677262801355, c_rs = 0.6203504908994001;
     const GridDev &g = a.g;
-    const int ix = (int)(t % g.nx);
-    const int64_t r = t / g.nx;
-    const int iy = (int)(r % g.ny);
-    const int iz = (int)(r / g.ny);
-    const double gx = fd_axis(a.n, t, ix, g.nx, 1, g.px, a.inv2h[0]);
-    const double gy = fd_axis(a.n, t, iy, g.ny, g.nx, g.py, a.inv2h[1]);
-    const double gz = fd_axis(a.n, t, iz, g.nz, (int64_t)g.nx * g.ny, g.pz, a.inv2h[2]);
+    double gx, gy, gz;
+    if (g.skew) {
+        grad_point(a.n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.Einv, gx, gy, gz);
+    } else {
+        const int ix = (int)(t % g.nx);
+        const int64_t r = t / g.nx;
+        const int iy = (int)(r % g.ny);
+        const int iz = (int)(r / g.ny);
+        gx = fd_axis(a.n, t, ix, g.nx, 1, g.px, a.inv2h[0]);
+        gy = fd_axis(a.n, t, iy, g.ny, g.nx, g.py, a.inv2h[1]);
+        gz = fd_axis(a.n, t, iz, g.nz, (int64_t)g.nx * g.ny, g.pz, a.inv2h[2]);
+    }
     const double g2 = gx * gx + gy * gy + gz * gz;
     const double cr = cbrt(nn);
     const double kF = c_kf * cr;
@@ -183,7 +188,7 @@ extern "C" int xc_energies(const vdw_grid *grid, const double *n_d, double n_flo
     hipLaunchKernelGGL(vdw::xc_kernel, dim3(blocks), dim3(vdw::kXcThreads), 0, s, a);
     VDW_HIP(hipGetLastError());
     hipLaunchKernelGGL(vdw::xc_reduce_kernel, dim3(1), dim3(vdw::kXcReduceThreads), 0, s, (const double *)a.part,
-                       blocks, g.hx * g.hy * g.hz, a.out);
+                       blocks, g.dV, a.out);
     VDW_HIP(hipGetLastError());
     double out[vdw::kXcTerms + 1];
     VDW_HIP(hipMemcpyAsync(out, a.out, sizeof(out), hipMemcpyDeviceToHost, s));

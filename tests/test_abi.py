@@ -51,10 +51,12 @@ def test_host_side_validation(L):
     assert lib.compute_q0(None, 1e-5, None, None, None, None, None, None) == L.VDW_EINVAL
     assert lib.compute_q0(ct.byref(g), 1e-5, None, None, None, None, None, None) == L.VDW_EINVAL
     assert b"NULL" in lib.vdw_last_error()
-    skew = L.VdwGrid.from_buffer_copy(g)
-    skew.cell[0][1] = 0.5
-    dummy = ct.c_void_p(16)
-    assert lib.compute_q0(ct.byref(skew), 1e-5, dummy, None, dummy, None, None, None) == L.VDW_EUNSUPPORTED
+    # a skew cell whose lattice vectors are linearly dependent
+    flat = L.VdwGrid.from_buffer_copy(g)
+    flat.cell[1][0], flat.cell[1][1] = 4.0, 0.0
+    dummy = ct.c_void_p(16)  # never dereferenced: every call below fails validation first
+    assert lib.compute_q0(ct.byref(flat), 1e-5, dummy, None, dummy, None, None, None) == L.VDW_EINVAL
+    assert b"degenerate" in lib.vdw_last_error()
     small = L.VdwGrid.from_buffer_copy(g)
     small.n[2] = 2
     assert lib.compute_q0(ct.byref(small), 1e-5, dummy, None, dummy, None, None, None) == L.VDW_EINVAL
@@ -87,6 +89,15 @@ def test_host_side_validation(L):
     assert lib.enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)) > 0
     o.j_chunks = 99
     assert lib.enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)) == 0
+    # skew cells are planned (general-metric kernels), except with Kahan runs
+    o.j_chunks = 0
+    skew = L.VdwGrid.from_buffer_copy(g)
+    skew.cell[1][0] = 1.5
+    assert lib.enl_workspace_size(ct.byref(skew), ct.byref(tp), ct.byref(o)) > 0
+    o.kahan = 1
+    o.precision = 1
+    assert lib.enl_workspace_size(ct.byref(skew), ct.byref(tp), ct.byref(o)) == 0
+    assert b"skew" in lib.vdw_last_error()
 
 
 def test_batch_plan_host_validation(L):

@@ -1,0 +1,181 @@
+"""GPU parity on skew (non-orthogonal) cells against the oracle: gradient and
+q0 point by point; energies and dE/dn element by element (FP64: 1e-12 /
+1e-10, FP32C: 1e-6 / 1e-4 in the L2 norm) for open and periodic cells, with
+images and a distance cut, for the generic (n_sigma = 16) and the n_sigma =
+64 kernels; the exchange-correlation energies; a batch that mixes a skew
+and an orthorhombic density; and the Xe slab on the hexagonal cell of the
+paper's sample run at full size (dE/dn at sampled points)."""
+import numpy as np
+import pytest
+
+import vdw_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CHEAP_RULE = dict(gl_points=6, graded_levels=8, kappa=2.0, A0=20.0)
+FP = {0: (1e-12, 1e-10), 1: (1e-6, 1e-4)}
+CELL = ((6.0, 0.0, 0.0), (2.3, 5.2, 0.0), (0.7, -0.6, 4.3))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0810_2273_amd as V
+
+    return V
+
+
+@pytest.fixture(scope="module")
+def tables(oracle):
+    out = {}
+    for nS, nD, Dmax in ((16, 256, 16.0), (64, 2048, 48.0)):
+        tp = oracle.table_params(n_D=nD, n_sigma=nS, D_max=Dmax, **CHEAP_RULE)
+        out[nS] = (tp, oracle.build_table(tp))
+    return out
+
+
+def _gpu_table(V, tp, tab):
+    import torch
+
+    params = V.TableParams(n_D=tp.n_D, n_sigma=tp.n_sigma, D_max=tp.D_max, gl_points=tp.gl_points,
+                           graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0)
+    t64 = torch.tensor(tab, dtype=torch.float64, device="cuda:0").contiguous()
+    return V.Table(params, t64, t64.float().contiguous())
+
+
+def _grids(V, oracle, wl):
+    return (V.Grid(wl.n, wl.h, wl.periodic, cell=wl.cell),
+            oracle.Grid(wl.n, wl.h, wl.periodic, cell=wl.cell))
+
+
+CASES = [
+    dict(periodic=(0, 0, 0), image_max=(0, 0, 0), r_cut=0.0),
+    dict(periodic=(1, 1, 0), image_max=(1, 1, 0), r_cut=0.0),
+    dict(periodic=(1, 0, 1), image_max=(2, 0, 1), r_cut=7.3),
+]
+
+
+def _wl(case, seed):
+    return W.random_skew(n=(18, 16, 13), cell=CELL, seed=seed, n_cut=2.2e-3, **case)
+
+
+@pytest.mark.parametrize("c", range(len(CASES)))
+def test_skew_gradient_and_q0(V, oracle, c):
+    import torch
+
+    wl = _wl(CASES[c], 40 + c)
+    g, og = _grids(V, oracle, wl)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    ref = oracle.compute_q0(og, wl.rho, wl.n_cut)
+    grad = qd["grad"].cpu().numpy().reshape(3, -1)
+    for a, k in enumerate(("gx", "gy", "gz")):
+        assert np.abs(grad[a] - ref[k]).max() <= 1e-12 * np.abs(ref[k]).max()
+    for k in ("q0", "dq_dn", "dq_dg"):
+        r = ref[k]
+        assert np.abs(qd[k].cpu().numpy() - r).max() <= 1e-12 * np.abs(r).max(), k
+
+
+@pytest.mark.parametrize("nS", [16, 64])
+@pytest.mark.parametrize("c", range(len(CASES)))
+def test_skew_energy_and_potential(V, oracle, tables, c, nS):
+    import torch
+
+    tp, tab = tables[nS]
+    wl = _wl(CASES[c], 50 + c)
+    g, og = _grids(V, oracle, wl)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    ref = oracle.evaluate(og, wl.rho, tab, tp, wl.n_cut, wl.image_max, wl.r_cut, potential=True)
+    table = _gpu_table(V, tp, tab)
+    for prec in (0, 1):
+        etol, vtol = FP[prec]
+        opts = V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec)
+        E, v = V.enl_potential(g, n, qd, table, opts)
+        v = v.cpu().numpy()
+        st = V.last_stats()
+        rel_e = abs(sum(E) - ref.E) / abs(ref.E)
+        rel_v = np.linalg.norm(v - ref.dEdn) / np.linalg.norm(ref.dEdn)
+        say(f"skew case {c} nS {nS} prec {prec}: N={st['retained']} threads={st['block_threads']} "
+            f"dE={rel_e:.1e} dv={rel_v:.1e}")
+        assert st["retained"] > 2048 and st["block_threads"] == 1024
+        assert rel_e <= etol
+        for a, b in ((E[0], ref.E_pair0), (E[1], ref.E_pairL), (E[2], ref.E_self)):
+            assert abs(a - b) <= etol * abs(ref.E) + 1e-300
+        assert rel_v <= vtol
+        Ee = V.enl_energy(g, n, qd["q0"], table, opts)
+        assert abs(sum(Ee) - sum(E)) <= 1e-12 * abs(sum(E))
+    with pytest.raises(V.VdwError):
+        V.enl_potential(g, n, qd, table, V.Opts(n_cut=wl.n_cut, precision=1, kahan=1))
+
+
+def test_skew_xc_energies(V, oracle):
+    import torch
+
+    wl = _wl(CASES[1], 60)
+    g, og = _grids(V, oracle, wl)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    E = V.xc_energies(g, n, 1e-12)
+    ref = oracle.xc_energies(og, wl.rho, 1e-12)
+    for k in ref:
+        assert E[k] == pytest.approx(ref[k], rel=1e-12), k
+
+
+def test_batch_mixing_skew_and_orthorhombic(V, oracle, tables):
+    """One batched launch over a skew and an orthorhombic density (the
+    general-metric kernel then serves both) equals the oracle per density."""
+    import torch
+
+    tp, tab = tables[64]
+    wls = [W.random_skew(n=(16, 14, 12), cell=CELL, seed=70, n_cut=2.2e-3),
+           W.random_small(n=(15, 17, 13), h=(0.35, 0.4, 0.3), seed=71, n_cut=2.2e-3)]
+    grids = [V.Grid(w.n, w.h, w.periodic, cell=w.cell) for w in wls]
+    ns = [torch.tensor(w.rho.reshape(-1), dtype=torch.float64, device="cuda:0") for w in wls]
+    npk, offs = V.pack_batch(grids, ns)
+    qd = V.compute_q0_batched(grids, npk, offs, wls[0].n_cut)
+    table = _gpu_table(V, tp, tab)
+    for prec in (0, 1):
+        etol, vtol = FP[prec]
+        Eb, vb = V.enl_potential_batched(grids, npk, offs, qd, table, V.Opts(n_cut=wls[0].n_cut, precision=prec))
+        vb = vb.cpu().numpy()
+        for b, w in enumerate(wls):
+            ref = oracle.evaluate(oracle.Grid(w.n, w.h, w.periodic, cell=w.cell), w.rho, tab, tp, w.n_cut,
+                                  potential=True)
+            assert abs(sum(Eb[b]) - ref.E) <= etol * abs(ref.E), (b, prec)
+            seg = vb[offs[b]:offs[b + 1]]
+            assert np.linalg.norm(seg - ref.dEdn) <= vtol * np.linalg.norm(ref.dEdn), (b, prec)
+
+
+@pytest.mark.parametrize("prec,vtol", [(1, 1e-4), (0, 1e-10)])
+def test_hex_slab_full_size_sampled_potential(V, oracle, tables, prec, vtol):
+    """Xe slab on the hexagonal cell (48 x 48 x 224, periodic in a and b,
+    images |m|, |p| <= 4, r <= 30 bohr): dE/dn at sampled points against the
+    oracle's rows for those points."""
+    import torch
+
+    tp, tab = tables[64]
+    wl = W.xe_hex_slab()
+    g, og = _grids(V, oracle, wl)
+    say(f"hex slab full size precision={prec}")
+    rng = np.random.default_rng(11)
+    rho = wl.rho.reshape(-1)
+    keep = np.flatnonzero(rho >= wl.n_cut)
+    ks = np.array(sorted(set(int(k) for k in list(rng.choice(keep, 16, replace=False)) + list(np.argsort(rho)[-3:]))))
+    n = torch.tensor(rho, dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    opts = V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec)
+    E, v = V.enl_potential(g, n, qd, _gpu_table(V, tp, tab), opts)
+    v = v.cpu().numpy()
+    say(f"  GPU E = {sum(E):.12e}  ({V.last_stats()['retained']} kept points)")
+    ref = oracle.potential_at(og, wl.rho, ks, tab, tp, wl.n_cut, wl.image_max, wl.r_cut)
+    rel = np.linalg.norm(v[ks] - ref) / np.linalg.norm(ref)
+    say(f"  sampled |dv|/|v| over {len(ks)} points = {rel:.3e}")
+    assert rel <= vtol
+    assert E[1] < 0
