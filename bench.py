@@ -56,7 +56,7 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--R", type=float, default=7.0, help="separation of the kr1 workload (bohr)")
-    p.add_argument("--workload", default="kr", choices=["kr", "kr1", "slab", "batch", "dimer24"],
+    p.add_argument("--workload", default="kr", choices=["kr", "kr1", "slab", "hexslab", "batch", "dimer24"],
                    help="kr: the Kr2-like dimer scan (the reported metric); kr1: one dimer at --R; slab, batch, "
                         "dimer24: the other cases")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
@@ -95,6 +95,11 @@ def workloads(a, W):
         wls = [W.xe_slab()]
         desc = ("Xe-like slab, 48x48x224 grid of an 8.6x8.6x40 bohr cell, periodic x,y, images |m|,|p|<=3, "
                 "r<=30 bohr, n_cut=1e-5, table 2048x64, energy + potential fused")
+    elif a.workload == "hexslab":
+        wls = [W.xe_hex_slab()]
+        desc = ("Xe-like slab on the hexagonal cell of a close-packed monolayer (a = (8.6, 0, 0), b = (4.3, 7.45, 0), "
+                "c = (0, 0, 40) bohr), 48x48x224 grid, periodic in a and b, images |m|,|p|<=4, r<=30 bohr, n_cut=1e-5, "
+                "table 2048x64, energy + potential fused")
     elif a.workload == "batch":
         wls = W.molecule_batch(64)
         desc = ("64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched "
@@ -157,7 +162,7 @@ def main():
     table = V.build_phi_table(tparams, device=dev)
     torch.cuda.synchronize()
     t_table = time.time() - t0
-    grids = [V.Grid(w.n, w.h, w.periodic) for w in wls]
+    grids = [V.Grid(w.n, w.h, w.periodic, cell=w.cell) for w in wls]
     ns = [torch.tensor(w.rho.reshape(-1), dtype=torch.float64, device=dev) for w in wls]
     n, offs = V.pack_batch(grids, ns)
     del ns
@@ -281,7 +286,7 @@ def main():
         "traffic": TRAFFIC_BYTES.get(a.workload) if a.workload != "kr1" or a.R == 7.0 else None,
         "kernel": "pair_kernel<%s, %s, %s>" % ("double" if a.workload == "dimer24" else "float",
                                                 "energy" if a.workload == "dimer24" else "ADJ",
-                                                "IMG" if a.workload == "slab" else "noIMG"),
+                                                "IMG" if a.workload in ("slab", "hexslab") else "noIMG"),
         "kernel_ms": kms32,
         "flop_per_unordered_pair": fpp,
     }

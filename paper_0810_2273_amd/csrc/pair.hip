@@ -69,7 +69,7 @@ struct Seg {
     int32_t skew, pad1;
     double einv[9];     // E^-1 (skew cells; gradient and its adjoint)
     double m01, m02, m12;  // skew: 2 e_x.e_y / h_x^2, 2 e_x.e_z / h_x^2, 2 e_y.e_z / h_x^2
-    double lmin, lmax;     // skew: extreme eigenvalues of the metric e_a.e_b / h_x^2
+    double en[9];          // skew: the step vectors e_a / h_x (row-major), for Cartesian tile boxes
     int64_t G, grid_off;
     int32_t nbx, nby, nbz, pad0;
     int64_t t_off, T;     // brick-order positions: offset (multiple of kCompactBlock), padded length
@@ -365,7 +365,8 @@ __device__ inline double wrot(double x)
 template <typename R>
 struct PairK {
     R tDmax, tDlds, tSclamp, csig, c4, casym, wy, wz;
-    R m01, m02, m12, lmin, lmax;  // skew cells (see Seg)
+    R m01, m02, m12;  // skew cells (see Seg)
+    R en[9];
     int S, nS, K;
 };
 
@@ -656,10 +657,27 @@ __device__ inline double uniform(double v)
     return __builtin_bit_cast(double, b);
 }
 
+// Position used for the tile boxes of the image pruning: the grid indices
+// on orthorhombic grids (the distance weights wy, wz apply), Cartesian
+// coordinates in units of h_x on skew grids (unit weights).
+template <typename R, int GEO>
+__device__ __forceinline__ void box_pos(const PairK<R> &k, R x, R y, R z, R &px, R &py, R &pz)
+{
+    if (GEO == kSkew) {
+        px = x * k.en[0] + y * k.en[3] + z * k.en[6];
+        py = x * k.en[1] + y * k.en[4] + z * k.en[7];
+        pz = x * k.en[2] + y * k.en[5] + z * k.en[8];
+    } else {
+        px = x;
+        py = y;
+        pz = z;
+    }
+}
+
 // Smallest and largest squared distance (units of h_x^2) between two boxes
-// whose grid-index ranges are given, after shifting the second by
-// (sx, sy, sz).  On skew grids the metric is bounded by its extreme
-// eigenvalues, which gives a lower and an upper bound.
+// of box_pos coordinates, after shifting the second by (sx, sy, sz).  On
+// skew grids the Cartesian boxes come from rounded products, so the bounds
+// are widened by 2^-12 relative.
 template <typename R, bool SKEW>
 __device__ inline void box_dist2(const PairK<R> &k, const R *bi, const R *bj, R sx, R sy, R sz, R &dmin2, R &dmax2)
 {
@@ -676,8 +694,8 @@ __device__ inline void box_dist2(const PairK<R> &k, const R *bi, const R *bj, R 
         dmax2 += wt[a] * far * far;
     }
     if (SKEW) {
-        dmin2 *= k.lmin;
-        dmax2 *= k.lmax;
+        dmin2 *= (R)(1.0 - 1.0 / 4096.0);
+        dmax2 *= (R)(1.0 + 1.0 / 4096.0);
     }
 }
 
@@ -758,8 +776,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
             kc.m01 = (R)sg.m01;
             kc.m02 = (R)sg.m02;
             kc.m12 = (R)sg.m12;
-            kc.lmin = (R)sg.lmin;
-            kc.lmax = (R)sg.lmax;
+            for (int k = 0; k < 9; ++k) kc.en[k] = (R)sg.en[k];
         }
         const R rcm = (R)(A.rc2 / (sg.hx * sg.hx));  // distance cut in units of h_x^2
         const Rec *__restrict__ P = recs + sg.p_off;
@@ -855,15 +872,19 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
             R ib[6] = {0, 0, 0, 0, 0, 0};
             if (prune) {
                 // bounding box of this wavefront's i-points
-                R lo[3] = {Ir[0].x, Ir[0].y, Ir[0].z}, hi[3] = {Ir[0].x, Ir[0].y, Ir[0].z};
+                R lo[3], hi[3];
+                box_pos<R, GEO>(kc, Ir[0].x, Ir[0].y, Ir[0].z, lo[0], lo[1], lo[2]);
+                hi[0] = lo[0];
+                hi[1] = lo[1];
+                hi[2] = lo[2];
 #pragma unroll
                 for (int p = 1; p < IPL; ++p) {
-                    lo[0] = min(lo[0], Ir[p].x);
-                    hi[0] = max(hi[0], Ir[p].x);
-                    lo[1] = min(lo[1], Ir[p].y);
-                    hi[1] = max(hi[1], Ir[p].y);
-                    lo[2] = min(lo[2], Ir[p].z);
-                    hi[2] = max(hi[2], Ir[p].z);
+                    R q[3];
+                    box_pos<R, GEO>(kc, Ir[p].x, Ir[p].y, Ir[p].z, q[0], q[1], q[2]);
+                    for (int a3 = 0; a3 < 3; ++a3) {
+                        lo[a3] = min(lo[a3], q[a3]);
+                        hi[a3] = max(hi[a3], q[a3]);
+                    }
                 }
                 for (int a3 = 0; a3 < 3; ++a3) {
                     ib[2 * a3] = uniform(wave_min<R>(lo[a3]));
@@ -876,12 +897,14 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 const Rec Jr = P[jv ? jj : J1 - 1];
                 R jb6[6] = {0, 0, 0, 0, 0, 0};
                 if (prune) {
-                    jb6[0] = uniform(wave_min<R>(Jr.x));
-                    jb6[1] = uniform(wave_max<R>(Jr.x));
-                    jb6[2] = uniform(wave_min<R>(Jr.y));
-                    jb6[3] = uniform(wave_max<R>(Jr.y));
-                    jb6[4] = uniform(wave_min<R>(Jr.z));
-                    jb6[5] = uniform(wave_max<R>(Jr.z));
+                    R q[3];
+                    box_pos<R, GEO>(kc, Jr.x, Jr.y, Jr.z, q[0], q[1], q[2]);
+                    jb6[0] = uniform(wave_min<R>(q[0]));
+                    jb6[1] = uniform(wave_max<R>(q[0]));
+                    jb6[2] = uniform(wave_min<R>(q[1]));
+                    jb6[3] = uniform(wave_max<R>(q[1]));
+                    jb6[4] = uniform(wave_min<R>(q[2]));
+                    jb6[5] = uniform(wave_max<R>(q[2]));
                 }
                 R jSc = 0, jSL = 0, jSq = 0;
                 for (int L = 0; L < nimg; ++L) {
@@ -894,8 +917,9 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                         home = (L == A.home);
                         if (prune) {
                             // r_i - r_j - L: the j box shifted by +L against the i box
-                            R dmin2, dmax2;
-                            box_dist2<R, GEO == kSkew>(kc, ib, jb6, lx, ly, lz, dmin2, dmax2);
+                            R dmin2, dmax2, cx, cy, cz;
+                            box_pos<R, GEO>(kc, lx, ly, lz, cx, cy, cz);
+                            box_dist2<R, GEO == kSkew>(kc, ib, jb6, cx, cy, cz, dmin2, dmax2);
                             if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
                             masked = dmax2 > rcm;
                         }
@@ -1258,33 +1282,6 @@ int64_t items_bound(int64_t G, int64_t BI, int64_t JC, int64_t ND)
 // when ND = BI / JC.
 int diag_items(int64_t BI, int64_t JC) { return BI > JC ? (int)(BI / JC) : 1; }
 
-// Bounds on the eigenvalues of a symmetric positive-definite 3 x 3 matrix
-// (trigonometric solution of the characteristic cubic, O. K. Smith, 1961),
-// widened by 1e-5 relative so the distance bounds built on them stay
-// conservative after rounding.
-void sym3_eig_bounds(const double M[3][3], double *lmin, double *lmax)
-{
-    const double p1 = M[0][1] * M[0][1] + M[0][2] * M[0][2] + M[1][2] * M[1][2];
-    const double q = (M[0][0] + M[1][1] + M[2][2]) / 3.0;
-    double e_min, e_max;
-    if (p1 == 0.0) {
-        e_min = fmin(M[0][0], fmin(M[1][1], M[2][2]));
-        e_max = fmax(M[0][0], fmax(M[1][1], M[2][2]));
-    } else {
-        const double d0 = M[0][0] - q, d1 = M[1][1] - q, d2 = M[2][2] - q;
-        const double p = sqrt((d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1) / 6.0);
-        const double B00 = d0 / p, B11 = d1 / p, B22 = d2 / p;
-        const double B01 = M[0][1] / p, B02 = M[0][2] / p, B12 = M[1][2] / p;
-        double r = 0.5 * (B00 * (B11 * B22 - B12 * B12) - B01 * (B01 * B22 - B12 * B02) + B02 * (B01 * B12 - B11 * B02));
-        r = fmin(1.0, fmax(-1.0, r));
-        const double phi = acos(r) / 3.0;
-        e_max = q + 2.0 * p * cos(phi);
-        e_min = q + 2.0 * p * cos(phi + 2.0 * 3.14159265358979323846 / 3.0);
-    }
-    *lmin = e_min * (1.0 - 1e-5);
-    *lmax = e_max * (1.0 + 1e-5);
-}
-
 // Compute units of the target (gfx950): the pair kernel runs one persistent
 // workgroup per CU, so the work list needs many more items than this to
 // keep every CU busy to the end.
@@ -1326,7 +1323,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             s.m01 = 2.0 * M[0][1];
             s.m02 = 2.0 * M[0][2];
             s.m12 = 2.0 * M[1][2];
-            sym3_eig_bounds(M, &s.lmin, &s.lmax);
+            for (int k = 0; k < 9; ++k) s.en[k] = g.E[k] / g.hx;
         }
         if (g.skew) P->skew = true;
         s.G = g.G;
