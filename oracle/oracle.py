@@ -227,6 +227,7 @@ class Grid:
     h: tuple  # (hx, hy, hz) bohr
     periodic: tuple = (0, 0, 0)
     cell: tuple | None = None
+    gradient: str = "fd"  # "fd", or "spectral": Fourier derivative on periodic axes (FD on the others)
 
     @property
     def G(self) -> int:
@@ -254,14 +255,14 @@ class Grid:
         return float(self.h[0] * self.h[1] * self.h[2])
 
 
-def grid_of_cell(n, cell, periodic=(0, 0, 0)) -> Grid:
+def grid_of_cell(n, cell, periodic=(0, 0, 0), gradient="fd") -> Grid:
     """Grid of an n[0] x n[1] x n[2] division of the cell (rows a, b, c); a
     diagonal cell gives the orthorhombic form."""
     c = np.asarray(cell, dtype=np.float64).reshape(3, 3)
     h = tuple(float(np.linalg.norm(c[a]) / n[a]) for a in range(3))
-    g = Grid(tuple(n), h, tuple(periodic), tuple(map(tuple, c)))
+    g = Grid(tuple(n), h, tuple(periodic), tuple(map(tuple, c)), gradient)
     if not g.skew:
-        return Grid(tuple(n), tuple(float(c[a, a] / n[a]) for a in range(3)), tuple(periodic))
+        return Grid(tuple(n), tuple(float(c[a, a] / n[a]) for a in range(3)), tuple(periodic), None, gradient)
     return g
 
 
@@ -302,21 +303,49 @@ def diff_matrix_1d(N: int, h: float, periodic: bool) -> sp.csr_matrix:
     return sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
 
 
+def fourier_wavenumbers(N: int, h: float) -> np.ndarray:
+    """2 pi m / (N h) for the DFT frequencies m = 0, 1, .., -1, with the
+    unpaired Nyquist frequency of an even N set to zero (its derivative is
+    not a real periodic function)."""
+    k = np.fft.fftfreq(N) * N * (2.0 * math.pi / (N * h))
+    if N % 2 == 0:
+        k[N // 2] = 0.0
+    return k
+
+
+def spectral_matrix_1d(N: int, h: float) -> sp.csr_matrix:
+    """The Fourier derivative on N periodic points of spacing h as a dense
+    N x N operator: column j is the derivative of the j-th unit vector,
+    computed by FFT (multiply by i k, transform back)."""
+    k = fourier_wavenumbers(N, h)
+    D = np.real(np.fft.ifft(1j * k[:, None] * np.fft.fft(np.eye(N), axis=0), axis=0))
+    return sp.csr_matrix(D)
+
+
+def _axis_op(grid: Grid, a: int, step: float):
+    N = grid.n[a]
+    if grid.gradient == "spectral" and grid.periodic[a]:
+        return spectral_matrix_1d(N, step)
+    return diff_matrix_1d(N, step, bool(grid.periodic[a]))
+
+
 def gradient_operators(grid: Grid):
     """Sparse G x G operators (Gx, Gy, Gz) on the flattened (x fastest) grid.
     On a skew grid the differences along the grid axes give d_a = e_a . grad n
-    (per grid step), and grad n = E^-1 d with E the matrix of step vectors."""
+    (per grid step), and grad n = E^-1 d with E the matrix of step vectors.
+    With grid.gradient == "spectral" the periodic axes take the Fourier
+    derivative instead of finite differences."""
     nx, ny, nz = grid.n
     Ix, Iy, Iz = sp.identity(nx), sp.identity(ny), sp.identity(nz)
     if grid.skew:
-        D = (sp.kron(Iz, sp.kron(Iy, diff_matrix_1d(nx, 1.0, bool(grid.periodic[0])))).tocsr(),
-             sp.kron(Iz, sp.kron(diff_matrix_1d(ny, 1.0, bool(grid.periodic[1])), Ix)).tocsr(),
-             sp.kron(diff_matrix_1d(nz, 1.0, bool(grid.periodic[2])), sp.kron(Iy, Ix)).tocsr())
+        D = (sp.kron(Iz, sp.kron(Iy, _axis_op(grid, 0, 1.0))).tocsr(),
+             sp.kron(Iz, sp.kron(_axis_op(grid, 1, 1.0), Ix)).tocsr(),
+             sp.kron(_axis_op(grid, 2, 1.0), sp.kron(Iy, Ix)).tocsr())
         Einv = np.linalg.inv(grid.steps)
         return tuple((Einv[c, 0] * D[0] + Einv[c, 1] * D[1] + Einv[c, 2] * D[2]).tocsr() for c in range(3))
-    Dx = diff_matrix_1d(nx, grid.h[0], bool(grid.periodic[0]))
-    Dy = diff_matrix_1d(ny, grid.h[1], bool(grid.periodic[1]))
-    Dz = diff_matrix_1d(nz, grid.h[2], bool(grid.periodic[2]))
+    Dx = _axis_op(grid, 0, grid.h[0])
+    Dy = _axis_op(grid, 1, grid.h[1])
+    Dz = _axis_op(grid, 2, grid.h[2])
     Gx = sp.kron(Iz, sp.kron(Iy, Dx)).tocsr()
     Gy = sp.kron(Iz, sp.kron(Dy, Ix)).tocsr()
     Gz = sp.kron(Dz, sp.kron(Iy, Ix)).tocsr()
@@ -324,9 +353,32 @@ def gradient_operators(grid: Grid):
 
 
 def gradient(grid: Grid, rho: np.ndarray):
-    """(dn/dx, dn/dy, dn/dz) on the flattened grid."""
+    """(dn/dx, dn/dy, dn/dz) on the flattened grid.  Fourier derivatives
+    (grid.gradient == "spectral", periodic axes) are taken by FFT along the
+    axis; the result equals gradient_operators(grid) applied to rho."""
     r = np.asarray(rho, dtype=np.float64).reshape(-1)
-    return tuple(G @ r for G in gradient_operators(grid))
+    if grid.gradient != "spectral" or not any(grid.periodic):
+        return tuple(G @ r for G in gradient_operators(grid))
+    nx, ny, nz = grid.n
+    f = r.reshape(nz, ny, nx)
+    steps = (1.0, 1.0, 1.0) if grid.skew else tuple(grid.h)
+    I = (sp.identity(nx), sp.identity(ny), sp.identity(nz))
+    d = []
+    for a in range(3):
+        if grid.periodic[a]:
+            ax = 2 - a
+            shape = [1, 1, 1]
+            shape[ax] = grid.n[a]
+            k = fourier_wavenumbers(grid.n[a], steps[a]).reshape(shape)
+            d.append(np.real(np.fft.ifft(1j * k * np.fft.fft(f, axis=ax), axis=ax)).reshape(-1))
+        else:
+            D1 = diff_matrix_1d(grid.n[a], steps[a], False)
+            op = (sp.kron(I[2], sp.kron(I[1], D1)), sp.kron(I[2], sp.kron(D1, I[0])), sp.kron(D1, sp.kron(I[1], I[0])))[a]
+            d.append(op.tocsr() @ r)
+    if not grid.skew:
+        return tuple(d)
+    Einv = np.linalg.inv(grid.steps)
+    return tuple(Einv[c, 0] * d[0] + Einv[c, 1] * d[1] + Einv[c, 2] * d[2] for c in range(3))
 
 
 # --------------------------------------------------------------------------
