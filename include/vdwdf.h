@@ -60,11 +60,20 @@ enum { VDW_FP64 = 0, VDW_FP32C = 1 };
  * axes and mapped to Cartesian components by the inverse of the step
  * matrix, and pair distances use the full metric e_a . e_b.  periodic[a] = 1
  * marks a periodic axis (the input's perx/pery/perz, App. A); images are
- * whole cell translations.  Every n[a] must be >= 3. */
+ * whole cell translations.  Every n[a] must be >= 3.
+ * gradient selects the derivative along periodic axes: VDW_GRAD_FD (0,
+ * second-order differences everywhere) or VDW_GRAD_SPECTRAL (1, the
+ * Fourier derivative, i.e. the FFT gradient of the paper's code, on
+ * periodic axes of at most 4096 points; open axes keep the differences).
+ * The spectral form is available to compute_q0, enl_energy, enl_potential
+ * and xc_energies, not to the batched calls and plans. */
+enum { VDW_GRAD_FD = 0, VDW_GRAD_SPECTRAL = 1 };
+
 typedef struct {
     int32_t n[3];
     double  cell[3][3];
     int32_t periodic[3];
+    int32_t gradient;
 } vdw_grid;
 
 /* The kernel table (Sec. 2; node counts and limits are free parameters,

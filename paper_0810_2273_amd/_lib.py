@@ -30,7 +30,8 @@ EXPORTS = (
 
 
 class VdwGrid(ct.Structure):
-    _fields_ = [("n", ct.c_int32 * 3), ("cell", (ct.c_double * 3) * 3), ("periodic", ct.c_int32 * 3)]
+    _fields_ = [("n", ct.c_int32 * 3), ("cell", (ct.c_double * 3) * 3), ("periodic", ct.c_int32 * 3),
+                ("gradient", ct.c_int32)]
 
 
 class VdwTableParams(ct.Structure):

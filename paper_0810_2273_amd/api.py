@@ -38,12 +38,14 @@ class TableParams:
 class Grid:
     """Equidistant grid, n points per axis, x fastest.  Orthorhombic with
     spacing h (bohr), or, with `cell` (rows: lattice vectors a, b, c in bohr),
-    any (skew) cell divided into n[0] x n[1] x n[2] steps (h is then unused)."""
+    any (skew) cell divided into n[0] x n[1] x n[2] steps (h is then unused).
+    gradient="spectral" takes the Fourier derivative on periodic axes."""
 
     n: tuple
     h: tuple = (0.0, 0.0, 0.0)
     periodic: tuple = (0, 0, 0)
     cell: tuple | None = None
+    gradient: str = "fd"  # "fd" or "spectral" (Fourier derivative on periodic axes)
 
     @property
     def G(self) -> int:
@@ -59,6 +61,9 @@ class Grid:
 
     def c(self) -> L.VdwGrid:
         g = L.VdwGrid()
+        if self.gradient not in ("fd", "spectral"):
+            raise ValueError("gradient must be 'fd' or 'spectral'")
+        g.gradient = 1 if self.gradient == "spectral" else 0
         for a in range(3):
             g.n[a] = int(self.n[a])
             g.periodic[a] = int(self.periodic[a])
@@ -149,7 +154,8 @@ def compute_q0(grid: Grid, n: torch.Tensor, n_cut: float, derivatives: bool = Tr
         raise ValueError("n does not match the grid")
     dev = n.device
     q0 = torch.empty(G, dtype=torch.float64, device=dev)
-    grad = torch.empty(3 * G, dtype=torch.float64, device=dev) if derivatives else None
+    # the spectral gradient stages its Fourier derivatives in the gradient planes
+    grad = torch.empty(3 * G, dtype=torch.float64, device=dev) if derivatives or grid.gradient == "spectral" else None
     dqdn = torch.empty(G, dtype=torch.float64, device=dev) if derivatives else None
     dqdg = torch.empty(G, dtype=torch.float64, device=dev) if derivatives else None
     g = grid.c()

@@ -21,7 +21,18 @@ struct GridDev {
     int32_t skew;
     double E[9], Einv[9];  // row-major; E[3a + c] = component c of e_a
     double dV;             // |det E|
+    int32_t spec[3];       // Fourier derivative on axis a (spectral gradient, periodic axis)
 };
+
+// ---- Fourier derivative along periodic axes (spectral.hip) ----
+// d_a per grid step of every line along `axis` of src (x fastest), written
+// to dst (same layout).
+int launch_spectral_lines(const GridDev &g, int axis, const double *src, double *dst, hipStream_t s);
+// Adjoint: dst[k] += sum_j D[j][k] B_a[j] along the lines of `axis`, with
+// B_a[j] = dEdq dqdg 2 (E^-T grad)_a at point j (1/h_a grad_a on
+// orthorhombic grids).
+int launch_spectral_adjoint(const GridDev &g, int axis, const double *dEdq, const double *dqdg, const double *grad,
+                            double *dst, hipStream_t s);
 
 // Set the thread-local error message and return `code`.
 int fail(int code, const char *fmt, ...);

@@ -67,6 +67,7 @@ struct Seg {
     int32_t nx, ny, nz, px, py, pz;
     double hx, hy, hz, dV;  // |e_a| (the unit of the kernel's distances is h_x = |e_x|), cell volume / G
     int32_t skew, pad1;
+    int32_t spec[3], pad2;  // Fourier derivative on axis a (its adjoint runs as line kernels)
     double einv[9];     // E^-1 (skew cells; gradient and its adjoint)
     double m01, m02, m12;  // skew: 2 e_x.e_y / h_x^2, 2 e_x.e_z / h_x^2, 2 e_y.e_z / h_x^2
     double en[9];          // skew: the step vectors e_a / h_x (row-major), for Cartesian tile boxes
@@ -1197,15 +1198,16 @@ __global__ __launch_bounds__(256) void assemble_kernel(AsmArgs A)
     const int64_t r = gl / s.nx;
     const int iy = (int)(r % s.ny);
     const int iz = (int)(r / s.ny);
-    double v;
+    // (axes with the Fourier derivative are added by their own line kernels)
+    double v = 0.0;
     if (s.skew) {
-        v = tstencil<true>(A, s, 0, gl, ix, s.nx, 1, s.px, 1.0);
-        v += tstencil<true>(A, s, 1, gl, iy, s.ny, s.nx, s.py, 1.0);
-        v += tstencil<true>(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, 1.0);
+        if (!s.spec[0]) v += tstencil<true>(A, s, 0, gl, ix, s.nx, 1, s.px, 1.0);
+        if (!s.spec[1]) v += tstencil<true>(A, s, 1, gl, iy, s.ny, s.nx, s.py, 1.0);
+        if (!s.spec[2]) v += tstencil<true>(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, 1.0);
     } else {
-        v = tstencil<false>(A, s, 0, gl, ix, s.nx, 1, s.px, s.hx);
-        v += tstencil<false>(A, s, 1, gl, iy, s.ny, s.nx, s.py, s.hy);
-        v += tstencil<false>(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, s.hz);
+        if (!s.spec[0]) v += tstencil<false>(A, s, 0, gl, ix, s.nx, 1, s.px, s.hx);
+        if (!s.spec[1]) v += tstencil<false>(A, s, 1, gl, iy, s.ny, s.nx, s.py, s.hy);
+        if (!s.spec[2]) v += tstencil<false>(A, s, 2, gl, iz, s.nz, (int64_t)s.nx * s.ny, s.pz, s.hz);
     }
     A.dEdn[t] += v;
 }
@@ -1224,7 +1226,7 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
     const Seg &s = segs[find_seg(segs, B, t, 4)];
     const int64_t o = s.grid_off;
     grad_q0_point(n + o, (long)(t - o), s.nx, s.ny, s.nz, s.px, s.py, s.pz, s.hx, s.hy, s.hz, s.skew ? s.einv : nullptr,
-                  (long)s.G, n_cut,
+                  nullptr, (long)s.G, n_cut,
                   grad ? grad + 3 * o : nullptr, q0 + o, dqdn ? dqdn + o : nullptr, dqdg ? dqdg + o : nullptr);
 }
 
@@ -1246,6 +1248,8 @@ struct Plan {
     int mimg[3] = {0, 0, 0};  // image range per axis (0 on open axes)
     bool img = false;
     bool skew = false;  // some density has a skew cell: the general-metric kernels
+    bool spec = false;  // the (single) density takes the Fourier derivative on some axis
+    GridDev g0;         // the first density's grid
     int JC = 8192;
     int tpb = kPairThreads;     // pair-kernel workgroup size
     int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
@@ -1292,6 +1296,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
 {
     P->segs.resize(B);
     P->skew = false;
+    P->spec = false;
     int64_t Gtot = 0;
     for (int b = 0; b < B; ++b) {
         GridDev g;
@@ -1326,6 +1331,11 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             for (int k = 0; k < 9; ++k) s.en[k] = g.E[k] / g.hx;
         }
         if (g.skew) P->skew = true;
+        for (int a = 0; a < 3; ++a) {
+            s.spec[a] = g.spec[a];
+            if (g.spec[a]) P->spec = true;
+        }
+        if (b == 0) P->g0 = g;
         s.G = g.G;
         s.grid_off = grid_off ? grid_off[b] : 0;
         if (grid_off && grid_off[b + 1] - grid_off[b] != g.G)
@@ -1333,6 +1343,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         Gtot += g.G;
     }
     if (Gtot > ((int64_t)1 << 31) - 1) return fail(VDW_EINVAL, "total grid size exceeds 2^31 - 1");
+    if (P->spec && B > 1) return fail(VDW_EUNSUPPORTED, "the spectral gradient is not available to batched calls");
     auto bound = [&](int64_t BI, int64_t JC) {
         int64_t n = 0;
         for (int b = 0; b < B; ++b) n += items_bound(P->segs[b].G, BI, JC, diag_items(BI, JC));
@@ -1788,8 +1799,22 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
         aa.dEdn = dEdn_d;
         hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((L.Gtot + 255) / 256)), dim3(256), 0, s, aa);
         VDW_HIP(hipGetLastError());
+        if (P.spec)  // a single density (batched calls reject the spectral gradient)
+            for (int a = 0; a < 3; ++a)
+                if (P.g0.spec[a]) {
+                    int rc = launch_spectral_adjoint(P.g0, a, dEdq, dqdg_d, grad_d, dEdn_d, s);
+                    if (rc) return rc;
+                }
     }
     return VDW_OK;
+}
+
+bool any_spectral(int B, const vdw_grid *grids)
+{
+    if (!grids || B < 1) return false;
+    for (int b = 0; b < B; ++b)
+        if (grids[b].gradient == VDW_GRAD_SPECTRAL) return true;
+    return false;
 }
 
 thread_local vdw_stats g_stats;
@@ -1902,6 +1927,7 @@ extern "C" int enl_potential_batched(int32_t B, const vdw_grid *grids, const int
     if (!grid_off) return fail(VDW_EINVAL, "grid_off is NULL");
     if (grid_off[0] != 0) return fail(VDW_EINVAL, "grid_off[0] must be 0");
     if (!dEdn_d) return fail(VDW_EINVAL, "dEdn_d is NULL");
+    if (any_spectral(B, grids)) return fail(VDW_EUNSUPPORTED, "the spectral gradient is not available to batched calls");
     return run(B, grids, grid_off, n_d, q0_d, grad_d, dq_dn_d, dq_dg_d, phi_d, phi_f, tp, opts, ws, ws_bytes, dEdn_d,
                E_out, (hipStream_t)stream);
 }
@@ -1936,6 +1962,7 @@ extern "C" int enl_batch_plan_create(int32_t B, const vdw_grid *grids, const int
     if (!grid_off) return fail(VDW_EINVAL, "grid_off is NULL");
     if (B >= 1 && grid_off[0] != 0) return fail(VDW_EINVAL, "grid_off[0] must be 0");
     if (potential != 0 && potential != 1) return fail(VDW_EINVAL, "potential must be 0 or 1");
+    if (any_spectral(B, grids)) return fail(VDW_EUNSUPPORTED, "the spectral gradient is not available to batch plans");
     vdw_batch_plan *p = new (std::nothrow) vdw_batch_plan;
     if (!p) return fail(VDW_ENOMEM, "out of host memory");
     int rc = prepare(B, grids, grid_off, tp, opts, potential, ws, ws_bytes, &p->E);

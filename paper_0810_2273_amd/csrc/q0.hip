@@ -18,8 +18,9 @@ __global__ __launch_bounds__(256) void grad_q0_kernel(GridDev g, double n_cut, c
 {
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= g.G) return;
-    grad_q0_point(n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.skew ? g.Einv : nullptr, g.G, n_cut,
-                  grad, q0, dqdn, dqdg);
+    const bool spec = g.spec[0] || g.spec[1] || g.spec[2];
+    grad_q0_point(n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.skew ? g.Einv : nullptr,
+                  spec ? g.spec : nullptr, g.G, n_cut, grad, q0, dqdn, dqdg);
 }
 
 }  // namespace
@@ -45,5 +46,14 @@ extern "C" int compute_q0(const vdw_grid *grid, double n_cut, const double *n_d,
     if (rc) return rc;
     if (!n_d || !q0_d) return vdw::fail(VDW_EINVAL, "n_d and q0_d must not be NULL");
     if (!(n_cut > 0.0) || !isfinite(n_cut)) return vdw::fail(VDW_EINVAL, "n_cut must be > 0");
+    if (g.spec[0] || g.spec[1] || g.spec[2]) {
+        // Fourier derivatives per grid step into the gradient planes first
+        if (!grad_d) return vdw::fail(VDW_EINVAL, "the spectral gradient needs grad_d");
+        for (int a = 0; a < 3; ++a)
+            if (g.spec[a]) {
+                rc = vdw::launch_spectral_lines(g, a, n_d, grad_d + a * g.G, (hipStream_t)stream);
+                if (rc) return rc;
+            }
+    }
     return vdw::launch_grad_q0(g, n_cut, n_d, grad_d, q0_d, dq_dn_d, dq_dg_d, 0, (hipStream_t)stream);
 }

@@ -43,24 +43,32 @@ __device__ inline double pw92_ec(double rs, double *dec)
 
 // Cartesian gradient at point t of an nx x ny x nz grid: differences along
 // the grid axes, divided by h_a on orthorhombic grids (einv = NULL), or per
-// grid step and mapped by E^-1 (row-major einv) on skew grids.
+// grid step and mapped by E^-1 (row-major einv) on skew grids.  With spec
+// (per-axis flags, or NULL) the derivative per grid step of a flagged axis
+// is read from plane a of pre (the Fourier derivative, computed before).
 __device__ inline void grad_point(const double *__restrict__ n, long t, int nx, int ny, int nz, int px, int py,
-                                  int pz, double hx, double hy, double hz, const double *einv, double &gx,
-                                  double &gy, double &gz)
+                                  int pz, double hx, double hy, double hz, const double *einv, const int *spec,
+                                  const double *pre, long G, double &gx, double &gy, double &gz)
 {
     int ix = (int)(t % nx);
     long r = t / nx;
     int iy = (int)(r % ny);
     int iz = (int)(r / ny);
-    if (!einv) {
+    if (!einv && !spec) {
         gx = fd_axis(n, t, ix, nx, 1, px, 0.5 / hx);
         gy = fd_axis(n, t, iy, ny, nx, py, 0.5 / hy);
         gz = fd_axis(n, t, iz, nz, (long)nx * ny, pz, 0.5 / hz);
         return;
     }
-    const double d0 = fd_axis(n, t, ix, nx, 1, px, 0.5);
-    const double d1 = fd_axis(n, t, iy, ny, nx, py, 0.5);
-    const double d2 = fd_axis(n, t, iz, nz, (long)nx * ny, pz, 0.5);
+    const double d0 = (spec && spec[0]) ? pre[t] : fd_axis(n, t, ix, nx, 1, px, 0.5);
+    const double d1 = (spec && spec[1]) ? pre[G + t] : fd_axis(n, t, iy, ny, nx, py, 0.5);
+    const double d2 = (spec && spec[2]) ? pre[2 * G + t] : fd_axis(n, t, iz, nz, (long)nx * ny, pz, 0.5);
+    if (!einv) {
+        gx = d0 / hx;
+        gy = d1 / hy;
+        gz = d2 / hz;
+        return;
+    }
     gx = einv[0] * d0 + einv[1] * d1 + einv[2] * d2;
     gy = einv[3] * d0 + einv[4] * d1 + einv[5] * d2;
     gz = einv[6] * d0 + einv[7] * d1 + einv[8] * d2;
@@ -68,14 +76,16 @@ __device__ inline void grad_point(const double *__restrict__ n, long t, int nx, 
 
 // Point t (x fastest) of an nx x ny x nz grid of G points whose density
 // starts at n: writes grad (3 planes of G, if non-null), q0, dq0/dn at fixed
-// |grad n|^2 and dq0/d|grad n|^2 (0 where n < n_cut).  einv as for grad_point.
+// |grad n|^2 and dq0/d|grad n|^2 (0 where n < n_cut).  einv and spec as for
+// grad_point; with spec the Fourier derivatives are read from grad (each
+// point reads its own entries before it overwrites them).
 __device__ inline void grad_q0_point(const double *__restrict__ n, long t, int nx, int ny, int nz, int px, int py,
-                                     int pz, double hx, double hy, double hz, const double *einv, long G,
-                                     double n_cut, double *__restrict__ grad, double *__restrict__ q0,
+                                     int pz, double hx, double hy, double hz, const double *einv, const int *spec,
+                                     long G, double n_cut, double *grad, double *__restrict__ q0,
                                      double *__restrict__ dqdn, double *__restrict__ dqdg)
 {
     double gx, gy, gz;
-    grad_point(n, t, nx, ny, nz, px, py, pz, hx, hy, hz, einv, gx, gy, gz);
+    grad_point(n, t, nx, ny, nz, px, py, pz, hx, hy, hz, einv, spec, grad, G, gx, gy, gz);
     if (grad) {
         grad[t] = gx;
         grad[G + t] = gy;

@@ -32,7 +32,11 @@ int validate_grid(const vdw_grid *g, GridDev *out)
         }
         if (g->periodic[a] != 0 && g->periodic[a] != 1)
             return fail(VDW_EINVAL, "periodic[%d] must be 0 or 1", a);
+        if (g->gradient == VDW_GRAD_SPECTRAL && g->periodic[a] && g->n[a] > 4096)
+            return fail(VDW_EINVAL, "spectral gradient: periodic axis %d has %d > 4096 points", a, g->n[a]);
     }
+    if (g->gradient != VDW_GRAD_FD && g->gradient != VDW_GRAD_SPECTRAL)
+        return fail(VDW_EINVAL, "gradient must be VDW_GRAD_FD or VDW_GRAD_SPECTRAL");
     double E[9];
     for (int a = 0; a < 3; ++a)
         for (int c = 0; c < 3; ++c) E[3 * a + c] = g->cell[a][c] / g->n[a];
@@ -59,6 +63,7 @@ int validate_grid(const vdw_grid *g, GridDev *out)
         out->pz = g->periodic[2];
         out->G = G;
         out->skew = skew;
+        for (int a = 0; a < 3; ++a) out->spec[a] = g->gradient == VDW_GRAD_SPECTRAL && g->periodic[a];
         for (int k = 0; k < 9; ++k) out->E[k] = E[k];
         if (!skew) {
             out->hx = g->cell[0][0] / g->n[0];

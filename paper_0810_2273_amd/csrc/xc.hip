@@ -29,6 +29,7 @@ struct XcArgs {
     int64_t chunk;    // grid points per block (multiple of kXcThreads)
     double *part;   // kXcTerms x blocks
     double *out;    // kXcTerms + 1 (the last: a non-finite flag)
+    const double *pre;  // spectral gradient: Fourier derivatives per grid step (3 planes), else NULL
 };
 
 // n eps for the five energies at one point (0 at or below the floor).
@@ -46,8 +47,9 @@ __device__ inline void xc_point(const XcArgs &a, int64_t t, double e[kXcTerms])
     const double c_kf = 3.0936677262801355, c_rs = 0.6203504908994001;
     const GridDev &g = a.g;
     double gx, gy, gz;
-    if (g.skew) {
-        grad_point(a.n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.Einv, gx, gy, gz);
+    if (g.skew || a.pre) {
+        grad_point(a.n, t, g.nx, g.ny, g.nz, g.px, g.py, g.pz, g.hx, g.hy, g.hz, g.skew ? g.Einv : nullptr,
+                   a.pre ? g.spec : nullptr, a.pre, g.G, gx, gy, gz);
     } else {
         const int ix = (int)(t % g.nx);
         const int64_t r = t / g.nx;
@@ -158,7 +160,9 @@ extern "C" size_t xc_workspace_size(const vdw_grid *grid)
     vdw::GridDev g;
     if (vdw::validate_grid(grid, &g)) return 0;
     const int blocks = vdw::xc_blocks(g.G);
-    return ((size_t)vdw::kXcTerms * blocks + vdw::kXcTerms + 1) * sizeof(double);
+    size_t bytes = ((size_t)vdw::kXcTerms * blocks + vdw::kXcTerms + 1) * sizeof(double);
+    if (g.spec[0] || g.spec[1] || g.spec[2]) bytes = (bytes + 255) / 256 * 256 + 3 * (size_t)g.G * sizeof(double);
+    return bytes;
 }
 
 extern "C" int xc_energies(const vdw_grid *grid, const double *n_d, double n_floor, void *ws, size_t ws_bytes,
@@ -184,6 +188,18 @@ extern "C" int xc_energies(const vdw_grid *grid, const double *n_d, double n_flo
     a.chunk = (per + vdw::kXcThreads - 1) / vdw::kXcThreads * vdw::kXcThreads;
     a.part = (double *)ws;
     a.out = a.part + (int64_t)vdw::kXcTerms * blocks;
+    a.pre = nullptr;
+    if (g.spec[0] || g.spec[1] || g.spec[2]) {
+        // Fourier derivatives per grid step of the periodic axes, before the energies
+        const size_t head = (((size_t)vdw::kXcTerms * blocks + vdw::kXcTerms + 1) * sizeof(double) + 255) / 256 * 256;
+        double *pre = (double *)((char *)ws + head);
+        for (int ax = 0; ax < 3; ++ax)
+            if (g.spec[ax]) {
+                rc = vdw::launch_spectral_lines(g, ax, n_d, pre + ax * g.G, s);
+                if (rc) return rc;
+            }
+        a.pre = pre;
+    }
     // blocks whose chunk starts beyond the grid (chunk rounding) write zero partials
     hipLaunchKernelGGL(vdw::xc_kernel, dim3(blocks), dim3(vdw::kXcThreads), 0, s, a);
     VDW_HIP(hipGetLastError());

@@ -171,3 +171,38 @@ def test_xc_host_side(L, oracle):
         oracle.recombine(e_nl, ec_lda, ec_pbe, Ex_pbe=ex_pbe, Ex_new=ex_rev, E_dft=-1234.5), abs=1e-9)
     assert math.isnan(lib.vdw_recombine(xc, e_nl, 0.0, 2))
     assert math.isnan(lib.vdw_recombine(None, e_nl, 0.0, 0))
+
+
+def test_spectral_gradient_host_validation(L):
+    """The gradient selector is validated, the spectral form needs the
+    gradient planes and a periodic axis of at most 4096 points, and the
+    batched calls and plans refuse it, all before any device work."""
+    lib = L.lib()
+    dummy = ct.c_void_p(16)  # never dereferenced
+    g = L.VdwGrid()
+    for a in range(3):
+        g.n[a] = 8
+        g.cell[a][a] = 4.0
+        g.periodic[a] = 1
+    g.gradient = 2
+    assert lib.compute_q0(ct.byref(g), 1e-5, dummy, dummy, dummy, None, None, None) == L.VDW_EINVAL
+    g.gradient = 1
+    assert lib.compute_q0(ct.byref(g), 1e-5, dummy, None, dummy, None, None, None) == L.VDW_EINVAL
+    assert b"grad_d" in lib.vdw_last_error()
+    long = L.VdwGrid.from_buffer_copy(g)
+    long.n[0] = 5000
+    assert lib.compute_q0(ct.byref(long), 1e-5, dummy, dummy, dummy, None, None, None) == L.VDW_EINVAL
+    tp = L.VdwTableParams(64, 16, 12.0, 8, 12, 4.0, 64.0)
+    o = L.VdwOpts()
+    o.n_cut = 1e-5
+    o.self_term = 1
+    o.table_lds_rows = -1
+    offs = (ct.c_int64 * 2)(0, 512)
+    E = (ct.c_double * 3)()
+    arr = (L.VdwGrid * 1)(g)
+    assert lib.enl_potential_batched(1, arr, offs, dummy, dummy, dummy, dummy, dummy, dummy, None, ct.byref(tp),
+                                     ct.byref(o), dummy, 1 << 30, dummy, E, None) == L.VDW_EUNSUPPORTED
+    plan = ct.c_void_p()
+    assert lib.enl_batch_plan_create(1, arr, offs, ct.byref(tp), ct.byref(o), 1, dummy, 1 << 30, ct.byref(plan),
+                                     None) == L.VDW_EUNSUPPORTED
+    assert lib.xc_workspace_size(ct.byref(g)) > 3 * 512 * 8
