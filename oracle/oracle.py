@@ -86,6 +86,8 @@ def lib():
     L.vo_pair_phi.argtypes = [d, d, d, dp, P(TableParams), dp]
     L.vo_self_phi.restype = d
     L.vo_self_phi.argtypes = [d, d, dp, P(TableParams), dp]
+    L.vo_self_voxel.restype = d
+    L.vo_self_voxel.argtypes = [d, dp, ct.c_int, dp, P(TableParams), dp]
     L.vo_pair_rows.restype = ct.c_int
     L.vo_pair_rows.argtypes = [
         ct.c_long, P(i32), P(i32), P(i32), dp, dp,
@@ -205,6 +207,30 @@ def self_phi(q, rho_s, tab, tp):
     dq = ct.c_double()
     v = lib().vo_self_phi(float(q), float(rho_s), _p(tab, ct.c_double), ct.byref(tp), ct.byref(dq))
     return float(v), dq.value
+
+
+VOXEL_GL_POINTS = 8  # Gauss-Legendre points per octant axis of the voxel rule
+
+
+def self_voxel(q, steps, tab, tp, g=VOXEL_GL_POINTS):
+    """The voxel double average Phi_V(q) of phi~(., 0) over the grid cell
+    spanned by the step vectors (rows of `steps`) and d Phi_V / d q."""
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    E = np.ascontiguousarray(np.asarray(steps, dtype=np.float64).reshape(9))
+    dq = ct.c_double()
+    v = lib().vo_self_voxel(float(q), _p(E, ct.c_double), int(g), _p(tab, ct.c_double), ct.byref(tp), ct.byref(dq))
+    return float(v), dq.value
+
+
+def onsite_phi(grid, q, tab, tp, self_term):
+    """The on-site value and its q-derivative: self_term 1 (or True) takes
+    phi~(q rho_s, 0) with the sphere radius of self_radius, 2 the voxel
+    double average, 0 (or False) nothing."""
+    if self_term is True or self_term == 1:
+        return self_phi(q, self_radius(grid.dV), tab, tp)
+    if self_term == 2:
+        return self_voxel(q, grid.steps, tab, tp)
+    return 0.0, 0.0
 
 
 # --------------------------------------------------------------------------
@@ -611,12 +637,11 @@ def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, se
     S0c, S0i, Sq = pair_rows(grid, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut)
     E0 = 0.5 * dV * dV * float(np.sum(nS * S0c))
     EL = 0.5 * dV * dV * float(np.sum(nS * S0i))
-    rs = self_radius(dV)
     Phi = np.zeros(len(nS))
     dPhi = np.zeros(len(nS))
     if self_term:
         for t in range(len(nS)):
-            Phi[t], dPhi[t] = self_phi(qS[t], rs, tab, tp)
+            Phi[t], dPhi[t] = onsite_phi(grid, qS[t], tab, tp, self_term)
     Es = 0.5 * dV * dV * float(np.sum(nS * nS * Phi))
     res = Result(E0, EL, Es, S0=S0c + S0i, Sq=Sq, q0=qd)
     if potential:
@@ -668,7 +693,6 @@ def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0
     P = np.array(sorted(pos[g] for g in touched if g in pos), dtype=np.int32)
     allS = np.arange(len(idx), dtype=np.int32)
     dV = grid.dV
-    rs = self_radius(dV)
 
     def part(rr):
         gx, gy, gz = (Ga @ rr for Ga in ops)
@@ -681,7 +705,7 @@ def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0
         e = 0.5 * dV * dV * (2.0 * R - PP)
         if self_term:
             for t in P:
-                e += 0.5 * dV * dV * nS[t] * nS[t] * self_phi(qS[t], rs, tab, tp)[0]
+                e += 0.5 * dV * dV * nS[t] * nS[t] * onsite_phi(grid, qS[t], tab, tp, self_term)[0]
         return e
 
     rp = r0.copy()
@@ -720,12 +744,11 @@ def potential_at(grid: Grid, rho, ks, tab, tp, n_cut, image_max=(0, 0, 0), r_cut
     else:
         S0c = S0i = Sq = np.zeros(0)
     dV = grid.dV
-    rs = self_radius(dV)
     dEdn_q = {}
     dEdq = {}
     for t, g in enumerate(gl):
         n = r[g]
-        Phi, dPhi = self_phi(qS[rows[t]], rs, tab, tp) if self_term else (0.0, 0.0)
+        Phi, dPhi = onsite_phi(grid, qS[rows[t]], tab, tp, self_term)
         dEdn_q[int(g)] = dV * dV * (S0c[t] + S0i[t] + n * Phi)
         dEdq[int(g)] = dV * dV * n * (Sq[t] + 0.5 * n * dPhi)
     out = np.zeros(len(ks))

@@ -341,6 +341,48 @@ double vo_self_phi(double q, double rho_s, const double *tab, const vo_table_par
     return v;
 }
 
+/* The voxel double average of the kernel at delta = 0,
+ *   Phi_V(q) = (1/dV^2) int_V int_V phi~(q |r - r'|, 0) dr dr'
+ *            = int_{[-1,1]^3} phi~(q |t_0 e_0 + t_1 e_1 + t_2 e_2|, 0) prod_a (1 - |t_a|) dt,
+ * V the grid cell spanned by the step vectors e_a (rows of E); the tent
+ * weight is the overlap of V with its translate by r - r'.  Rule: the 8
+ * octants, in each t_a = +-u_a^2 with u_a at the g Gauss-Legendre nodes of
+ * [0, 1], node weight prod_a 2 u_a w_a (1 - u_a^2) (the substitution
+ * clusters nodes at the log singularity of phi~ at r = r').  Also returns
+ * d Phi_V / d q. */
+double vo_self_voxel(double q, const double E[9], int g, const double *tab, const vo_table_params *p,
+                     double *dphi_dq)
+{
+    double x[64], w[64];
+    if (g < 1 || g > 64) return NAN;
+    vo_gauss_legendre(g, x, w);
+    double u[64], wt[64];
+    for (int k = 0; k < g; ++k) {
+        u[k] = 0.5 * (x[k] + 1.0);  /* [-1, 1] -> [0, 1] */
+        double wk = 0.5 * w[k];
+        wt[k] = 2.0 * u[k] * wk * (1.0 - u[k] * u[k]);
+    }
+    double acc = 0.0, dacc = 0.0;
+    for (int oct = 0; oct < 8; ++oct) {
+        const double s0 = (oct & 1) ? -1.0 : 1.0, s1 = (oct & 2) ? -1.0 : 1.0, s2 = (oct & 4) ? -1.0 : 1.0;
+        for (int i = 0; i < g; ++i)
+            for (int j = 0; j < g; ++j)
+                for (int k = 0; k < g; ++k) {
+                    const double t0 = s0 * u[i] * u[i], t1 = s1 * u[j] * u[j], t2 = s2 * u[k] * u[k];
+                    const double rx = t0 * E[0] + t1 * E[3] + t2 * E[6];
+                    const double ry = t0 * E[1] + t1 * E[4] + t2 * E[7];
+                    const double rz = t0 * E[2] + t1 * E[5] + t2 * E[8];
+                    const double r = sqrt(rx * rx + ry * ry + rz * rz);
+                    const double wn = wt[i] * wt[j] * wt[k];
+                    double d;
+                    acc += wn * vo_self_phi(q, r, tab, p, &d);
+                    dacc += wn * d;
+                }
+    }
+    if (dphi_dq) *dphi_dq = dacc;
+    return acc;
+}
+
 /* ------------------------------------------------------------------ */
 /* Row sums of the double sum of Eq. (2).                                */
 /*                                                                        */
