@@ -107,7 +107,8 @@ typedef struct {
     int32_t image_max[3];   /* images |m_a| <= image_max[a] on periodic axes      */
     int32_t precision;      /* VDW_FP64 or VDW_FP32C (FP32 pair terms with
                                compensated FP32 runs carried in FP64)             */
-    int32_t self_term;      /* 1: add the on-site term E_self (below); 0: omit     */
+    int32_t self_term;      /* on-site term E_self (below): 1 the sphere form,
+                               2 the voxel double average, 0 none             */
     int32_t table_lds_rows; /* rows of the table kept in LDS; -1: as many as fit  */
     int32_t block_threads;  /* pair-kernel workgroup size: 1024 (row blocks of
                                4096 points for FP32C with n_sigma = 64 and no
@@ -216,8 +217,15 @@ size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, cons
  * D < D_max and -C/(d1^2 d2^2 (d1^2 + d2^2)), C = 12 (4 pi/9)^3, beyond:
  *   E_pair0 = 1/2 dV^2 sum_{i != j in S} n_i n_j phi~(q_i, q_j, |r_i - r_j|)
  *   E_pairL = 1/2 dV^2 sum_{i, j in S} sum_{L != 0} n_i n_j phi~(.., |r_i - r_j - L|)
- *   E_self  = 1/2 dV^2 sum_{i in S} n_i^2 phi~(q_i rho_s, 0),
- *             rho_s = (3 dV / 4 pi)^(1/3) e^(-1/3)     (if opts->self_term)
+ *   E_self  = 1/2 dV^2 sum_{i in S} n_i^2 Phi(q_i), with (opts->self_term)
+ *     1: Phi(q) = phi~(q rho_s, 0), rho_s = (3 dV / 4 pi)^(1/3) e^(-1/3)
+ *        (the log kernel averaged over the sphere of volume dV);
+ *     2: Phi(q) = int_{[-1,1]^3} phi~(q |sum_a t_a e_a|, 0) prod_a (1 - |t_a|) dt,
+ *        the double average over the grid cell (e_a its step vectors), by
+ *        8 octants with t_a = +-u^2 at 8 Gauss-Legendre nodes u of [0, 1]
+ *        (4096 kernel values per kept point; a reading of the paper's phi0
+ *        step, App. A);
+ *     0: none.
  * L runs over the images selected by opts->image_max on periodic axes
  * (Sec. 3, periodic problems), and every (i, j, L) with a distance above
  * opts->r_cut (if > 0) is dropped.  dV = |det(cell)| / G (hx hy hz on

@@ -88,6 +88,8 @@ def lib():
     L.vo_self_phi.argtypes = [d, d, dp, P(TableParams), dp]
     L.vo_self_voxel.restype = d
     L.vo_self_voxel.argtypes = [d, dp, ct.c_int, dp, P(TableParams), dp]
+    L.vo_self_voxel_many.restype = ct.c_int
+    L.vo_self_voxel_many.argtypes = [ct.c_long, dp, dp, ct.c_int, dp, P(TableParams), dp, dp]
     L.vo_pair_rows.restype = ct.c_int
     L.vo_pair_rows.argtypes = [
         ct.c_long, P(i32), P(i32), P(i32), dp, dp,
@@ -220,6 +222,18 @@ def self_voxel(q, steps, tab, tp, g=VOXEL_GL_POINTS):
     dq = ct.c_double()
     v = lib().vo_self_voxel(float(q), _p(E, ct.c_double), int(g), _p(tab, ct.c_double), ct.byref(tp), ct.byref(dq))
     return float(v), dq.value
+
+
+def self_voxel_many(q, steps, tab, tp, g=VOXEL_GL_POINTS):
+    """self_voxel at every value of the array q: (Phi_V, dPhi_V/dq)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    E = np.ascontiguousarray(np.asarray(steps, dtype=np.float64).reshape(9))
+    phi = np.zeros(len(q))
+    dphi = np.zeros(len(q))
+    lib().vo_self_voxel_many(len(q), _p(q, ct.c_double), _p(E, ct.c_double), int(g), _p(tab, ct.c_double),
+                             ct.byref(tp), _p(phi, ct.c_double), _p(dphi, ct.c_double))
+    return phi, dphi
 
 
 def onsite_phi(grid, q, tab, tp, self_term):
@@ -639,7 +653,9 @@ def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, se
     EL = 0.5 * dV * dV * float(np.sum(nS * S0i))
     Phi = np.zeros(len(nS))
     dPhi = np.zeros(len(nS))
-    if self_term:
+    if self_term == 2:
+        Phi, dPhi = self_voxel_many(qS, grid.steps, tab, tp)
+    elif self_term:
         for t in range(len(nS)):
             Phi[t], dPhi[t] = onsite_phi(grid, qS[t], tab, tp, self_term)
     Es = 0.5 * dV * dV * float(np.sum(nS * nS * Phi))

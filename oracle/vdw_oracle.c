@@ -383,6 +383,19 @@ double vo_self_voxel(double q, const double E[9], int g, const double *tab, cons
     return acc;
 }
 
+/* vo_self_voxel at many q values (one thread per value). */
+int vo_self_voxel_many(long m, const double *q, const double E[9], int g, const double *tab,
+                       const vo_table_params *p, double *phi, double *dphi_dq)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long t = 0; t < m; ++t) {
+        double d;
+        phi[t] = vo_self_voxel(q[t], E, g, tab, p, &d);
+        if (dphi_dq) dphi_dq[t] = d;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Row sums of the double sum of Eq. (2).                                */
 /*                                                                        */

@@ -58,6 +58,7 @@ struct DevInfo {
 int device_info(DevInfo *out);
 
 // ---- table builder (table.hip) ----
+void gauss_legendre_nodes(int n, double *x, double *w);  // host; ascending nodes on [-1, 1]
 int launch_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, hipStream_t s);
 
 // ---- gradient and q0 (q0.hip) ----

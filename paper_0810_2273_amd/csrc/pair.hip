@@ -69,6 +69,7 @@ struct Seg {
     int32_t skew, pad1;
     int32_t spec[3], pad2;  // Fourier derivative on axis a (its adjoint runs as line kernels)
     double einv[9];     // E^-1 (skew cells; gradient and its adjoint)
+    double e[9];        // the step vectors e_a (rows; diag(h) on orthorhombic cells), for the voxel term
     double m01, m02, m12;  // skew: 2 e_x.e_y / h_x^2, 2 e_x.e_z / h_x^2, 2 e_y.e_z / h_x^2
     double en[9];          // skew: the step vectors e_a / h_x (row-major), for Cartesian tile boxes
     int64_t G, grid_off;
@@ -983,6 +984,8 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
 // finalize, reduce, assemble
 // ---------------------------------------------------------------------------
 
+constexpr int kVoxelGL = 8;  // Gauss-Legendre points per octant axis of the voxel on-site rule
+
 struct FinArgs {
     const Seg *segs;
     int B;
@@ -994,6 +997,8 @@ struct FinArgs {
     int64_t istride, jstride;
     int JC, BI, ND, NI, NJ;
     int img, adj, self_term;
+    int vg;                   // voxel term: Gauss-Legendre points per octant axis
+    double vu[kVoxelGL], vw[kVoxelGL];  // voxel term: nodes u in (0, 1) and weights 2 u w (1 - u^2)
     const int32_t *gidx;
     const double *n, *q0, *dqdn;
     const double *tab;  // FP64 table for the on-site term
@@ -1019,6 +1024,34 @@ __device__ inline double self_phi(const FinArgs &F, double D, double *dphi)
     double p0 = F.tab[(int64_t)k * F.nS], p1 = F.tab[(int64_t)(k + 1) * F.nS];
     *dphi = (p1 - p0) / F.dD;
     return p0 + fD * (p1 - p0);
+}
+
+// The voxel double average of phi~(., 0) over the grid cell spanned by the
+// step vectors e (rows):
+//   Phi_V(q) = int_{[-1,1]^3} phi~(q |sum_a t_a e_a|, 0) prod_a (1 - |t_a|) dt,
+// by the rule of 8 octants with t_a = +-u^2 at the Gauss-Legendre nodes u of
+// [0, 1] (node weight prod 2 u w (1 - u^2)); *dPhi = d Phi_V / d q.
+__device__ inline double voxel_phi(const FinArgs &F, const double *e, double q, double *dPhi)
+{
+    double acc = 0.0, dacc = 0.0;
+    for (int oct = 0; oct < 8; ++oct) {
+        const double s0 = (oct & 1) ? -1.0 : 1.0, s1 = (oct & 2) ? -1.0 : 1.0, s2 = (oct & 4) ? -1.0 : 1.0;
+        for (int i = 0; i < F.vg; ++i)
+            for (int j = 0; j < F.vg; ++j)
+                for (int k = 0; k < F.vg; ++k) {
+                    const double t0 = s0 * F.vu[i] * F.vu[i], t1 = s1 * F.vu[j] * F.vu[j], t2 = s2 * F.vu[k] * F.vu[k];
+                    const double rx = t0 * e[0] + t1 * e[3] + t2 * e[6];
+                    const double ry = t0 * e[1] + t1 * e[4] + t2 * e[7];
+                    const double rz = t0 * e[2] + t1 * e[5] + t2 * e[8];
+                    const double r = sqrt(rx * rx + ry * ry + rz * rz);
+                    const double w = F.vw[i] * F.vw[j] * F.vw[k];
+                    double dD;
+                    acc += w * self_phi(F, q * r, &dD);
+                    dacc += w * r * dD;
+                }
+    }
+    *dPhi = dacc;
+    return acc;
 }
 
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
@@ -1064,7 +1097,9 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         const double nn = F.n[g], q = F.q0[g];
         const double rho_s = cbrt(3.0 * sg.dV / (4.0 * 3.14159265358979323846)) * exp(-1.0 / 3.0);
         double Phi = 0.0, dPhi = 0.0;
-        if (F.self_term) {
+        if (F.self_term == 2) {
+            Phi = voxel_phi(F, sg.e, q, &dPhi);
+        } else if (F.self_term) {
             double dphi_dD;
             Phi = self_phi(F, q * rho_s, &dphi_dD);
             dPhi = rho_s * dphi_dD;
@@ -1286,6 +1321,19 @@ int64_t items_bound(int64_t G, int64_t BI, int64_t JC, int64_t ND)
 // when ND = BI / JC.
 int diag_items(int64_t BI, int64_t JC) { return BI > JC ? (int)(BI / JC) : 1; }
 
+// Nodes and weights of the voxel on-site rule: the kVoxelGL-point
+// Gauss-Legendre rule mapped to [0, 1], each weight times 2 u (1 - u^2) for
+// the substitution t = u^2 and the tent 1 - t.
+void voxel_rule(double *u, double *wt)
+{
+    double x[kVoxelGL], w[kVoxelGL];
+    gauss_legendre_nodes(kVoxelGL, x, w);
+    for (int j = 0; j < kVoxelGL; ++j) {
+        u[j] = 0.5 * (x[j] + 1.0);
+        wt[j] = 2.0 * u[j] * (0.5 * w[j]) * (1.0 - u[j] * u[j]);
+    }
+}
+
 // Compute units of the target (gfx950): the pair kernel runs one persistent
 // workgroup per CU, so the work list needs many more items than this to
 // keep every CU busy to the end.
@@ -1318,6 +1366,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         s.dV = g.dV;
         s.skew = g.skew;
         for (int k = 0; k < 9; ++k) s.einv[k] = g.Einv[k];
+        for (int k = 0; k < 9; ++k) s.e[k] = g.E[k];
         {
             // metric e_a.e_b / h_x^2 (diagonal on orthorhombic cells)
             double M[3][3];
@@ -1474,7 +1523,7 @@ int validate_opts(const vdw_opts *o)
     if (!o) return fail(VDW_EINVAL, "opts is NULL");
     if (!(o->n_cut > 0.0) || !isfinite(o->n_cut)) return fail(VDW_EINVAL, "n_cut must be > 0");
     if (o->precision != VDW_FP64 && o->precision != VDW_FP32C) return fail(VDW_EINVAL, "precision must be 0 or 1");
-    if (o->self_term != 0 && o->self_term != 1) return fail(VDW_EINVAL, "self_term must be 0 or 1");
+    if (o->self_term < 0 || o->self_term > 2) return fail(VDW_EINVAL, "self_term must be 0, 1 or 2");
     if (o->block_threads != 0 && o->block_threads != 1024 && o->block_threads != 512 && o->block_threads != 256)
         return fail(VDW_EINVAL, "block_threads must be 0, 256, 512 or 1024");
     if (o->j_chunks < 0 || o->j_chunks > 64) return fail(VDW_EINVAL, "j_chunks must be in 0..64");
@@ -1770,6 +1819,8 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.img = P.img ? 1 : 0;
     fa.adj = E.adj;
     fa.self_term = E.self_term;
+    fa.vg = kVoxelGL;
+    voxel_rule(fa.vu, fa.vw);
     fa.gidx = gidx;
     fa.n = n_d;
     fa.q0 = q0_d;

@@ -209,6 +209,10 @@ __global__ void phi_to_f32_kernel(long total, const double *__restrict__ phi, fl
 
 }  // namespace
 
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1], for other parts of
+// the library.
+void gauss_legendre_nodes(int n, double *x, double *w) { legendre_nodes(n, x, w); }
+
 int launch_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, hipStream_t s)
 {
     TableArgs a;

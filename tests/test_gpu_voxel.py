@@ -1,0 +1,105 @@
+"""GPU parity of the voxel on-site term (self_term = 2) against the oracle:
+energies and dE/dn element by element (FP64: 1e-12 / 1e-10, FP32C: 1e-6 /
+1e-4) on an orthorhombic and a skew grid, and E_self of the 96^3 Kr dimer
+in the bench launch configuration against the oracle's rule at sampled
+points (the term is per point)."""
+import numpy as np
+import pytest
+
+import vdw_workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CHEAP_RULE = dict(gl_points=6, graded_levels=8, kappa=2.0, A0=20.0)
+FP = {0: (1e-12, 1e-10), 1: (1e-6, 1e-4)}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0810_2273_amd as V
+
+    return V
+
+
+@pytest.fixture(scope="module")
+def tt(oracle):
+    tp = oracle.table_params(n_D=256, n_sigma=16, D_max=16.0, **CHEAP_RULE)
+    return tp, oracle.build_table(tp)
+
+
+def _gpu_table(V, tp, tab):
+    import torch
+
+    params = V.TableParams(n_D=tp.n_D, n_sigma=tp.n_sigma, D_max=tp.D_max, gl_points=tp.gl_points,
+                           graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0)
+    t64 = torch.tensor(tab, dtype=torch.float64, device="cuda:0").contiguous()
+    return V.Table(params, t64, t64.float().contiguous())
+
+
+@pytest.mark.parametrize("skew", [False, True])
+def test_voxel_term_energy_and_potential(V, oracle, tt, skew):
+    import torch
+
+    tp, tab = tt
+    if skew:
+        wl = W.random_skew(n=(16, 14, 12), cell=((5.2, 0, 0), (2.0, 4.6, 0), (0.6, -0.5, 4.0)), periodic=(1, 0, 0),
+                           seed=90, n_cut=2.2e-3, image_max=(1, 0, 0))
+    else:
+        wl = W.random_small(n=(17, 15, 13), h=(0.35, 0.4, 0.3), seed=91, n_cut=2.2e-3)
+    g = V.Grid(wl.n, wl.h, wl.periodic, cell=wl.cell)
+    og = oracle.Grid(wl.n, wl.h, wl.periodic, cell=wl.cell)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    ref = oracle.evaluate(og, wl.rho, tab, tp, wl.n_cut, wl.image_max, 0.0, self_term=2, potential=True)
+    sph = oracle.evaluate(og, wl.rho, tab, tp, wl.n_cut, wl.image_max, 0.0, self_term=1)
+    assert abs(ref.E_self - sph.E_self) > 1e-6 * abs(sph.E_self)  # a different on-site term
+    table = _gpu_table(V, tp, tab)
+    for prec in (0, 1):
+        etol, vtol = FP[prec]
+        E, v = V.enl_potential(g, n, qd, table, V.Opts(n_cut=wl.n_cut, image_max=wl.image_max, precision=prec,
+                                                       self_term=2))
+        v = v.cpu().numpy()
+        say(f"voxel skew={skew} prec {prec}: E_self {E[2]:.12e} vs {ref.E_self:.12e}")
+        assert abs(E[2] - ref.E_self) <= 1e-12 * abs(ref.E_self)  # per-point FP64 in both precisions
+        assert abs(sum(E) - ref.E) <= etol * abs(ref.E)
+        assert np.linalg.norm(v - ref.dEdn) <= vtol * np.linalg.norm(ref.dEdn)
+
+
+def test_voxel_term_full_size(V, oracle):
+    """96^3 Kr dimer (576 596 kept points): E_self of the voxel term from the
+    GPU against the oracle's rule over every kept point (q0 from the oracle,
+    equal to the GPU's to rounding); the pair energies do not change."""
+    import time
+
+    import torch
+
+    tp = oracle.table_params(n_D=2048, n_sigma=64, D_max=48.0, **CHEAP_RULE)
+    tab = oracle.build_table(tp)
+    wl = W.kr_dimer(7.0)
+    g = V.Grid(wl.n, wl.h, wl.periodic)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    table = _gpu_table(V, tp, tab)
+    E1 = V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, precision=1, self_term=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E2 = V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, precision=1, self_term=2))
+    dt = time.perf_counter() - t0
+    say(f"96^3 dimer: E_self sphere {E1[2]:.10e}, voxel {E2[2]:.10e}, call {dt:.3f} s")
+    assert E1[0] == E2[0] and E1[1] == E2[1]
+    og = oracle.Grid(wl.n, wl.h, wl.periodic)
+    r = wl.rho.reshape(-1)
+    q = oracle.compute_q0(og, r, wl.n_cut)["q0"]
+    keep = np.flatnonzero(r >= wl.n_cut)
+    phi, _ = oracle.self_voxel_many(q[keep], og.steps, tab, tp)
+    ref = 0.5 * og.dV ** 2 * float(np.sum(r[keep] ** 2 * phi))
+    say(f"  oracle E_self (voxel) {ref:.10e}")
+    assert E2[2] == pytest.approx(ref, rel=1e-11)
