@@ -42,11 +42,13 @@ class TableParams(ct.Structure):
         ("graded_levels", ct.c_int32),
         ("kappa", ct.c_double),
         ("A0", ct.c_double),
+        ("interp", ct.c_int32),
     ]
 
 
-def table_params(n_D=1024, n_sigma=32, D_max=48.0, gl_points=8, graded_levels=12, kappa=4.0, A0=64.0):
-    return TableParams(n_D, n_sigma, D_max, gl_points, graded_levels, kappa, A0)
+def table_params(n_D=1024, n_sigma=32, D_max=48.0, gl_points=8, graded_levels=12, kappa=4.0, A0=64.0, interp=0):
+    """interp: 0 bilinear, 1 cubic (C1) in D and linear in sigma."""
+    return TableParams(n_D, n_sigma, D_max, gl_points, graded_levels, kappa, A0, interp)
 
 
 def lib():

@@ -43,6 +43,7 @@ typedef struct {
     int32_t graded_levels;  /* number of halving panels below pi/2               */
     double  kappa;          /* cut-off A >= kappa * max(d1, d2)                  */
     double  A0;             /* cut-off A >= A0                                   */
+    int32_t interp;         /* 0: bilinear; 1: cubic (C1) in D, linear in sigma  */
 } vo_table_params;
 
 static const double VO_PI = 3.14159265358979323846;
@@ -275,12 +276,57 @@ int vo_table_nodes(const vo_table_params *p, long count, const int32_t *k, const
 /* Interpolated kernel.                                                  */
 /* ------------------------------------------------------------------ */
 
-/* Bilinear interpolation of the table at (D, sigma), D < D_max, with
- * the partial derivatives of the interpolant in D and sigma. */
+/* Column l of the table at rows k-1 .. k+2 for the cubic form, with the rows
+ * beyond the table ends extrapolated linearly (phi_{-1} = 2 phi_0 - phi_1,
+ * phi_{nD} = 2 phi_{nD-1} - phi_{nD-2}). */
+static double vo_row(const double *tab, int nD, int nS, int row, int l)
+{
+    if (row < 0) return 2.0 * tab[(long)l] - tab[(long)nS + l];
+    if (row > nD - 1) return 2.0 * tab[(long)(nD - 1) * nS + l] - tab[(long)(nD - 2) * nS + l];
+    return tab[(long)row * nS + l];
+}
+
+/* Cubic Hermite interpolation on [0, 1] between f1 and f2 with the
+ * Catmull-Rom tangents (f2 - f0)/2 and (f3 - f1)/2, and its derivative. */
+static double vo_catmull_rom(double f0, double f1, double f2, double f3, double t, double *dt)
+{
+    const double m1 = 0.5 * (f2 - f0), m2 = 0.5 * (f3 - f1);
+    const double t2 = t * t, t3 = t2 * t;
+    const double h00 = 2 * t3 - 3 * t2 + 1, h10 = t3 - 2 * t2 + t, h01 = -2 * t3 + 3 * t2, h11 = t3 - t2;
+    if (dt) *dt = (6 * t2 - 6 * t) * f1 + (3 * t2 - 4 * t + 1) * m1 + (-6 * t2 + 6 * t) * f2 + (3 * t2 - 2 * t) * m2;
+    return h00 * f1 + h10 * m1 + h01 * f2 + h11 * m2;
+}
+
+/* Interpolation of the table at (D, sigma), D < D_max, with the partial
+ * derivatives of the interpolant in D and sigma: bilinear (interp = 0), or
+ * (interp = 1) cubic in D through the Catmull-Rom form of each of the two
+ * sigma columns, which makes the interpolant C1 in D, then linear in sigma. */
 double vo_table_interp(const double *tab, const vo_table_params *p, double D, double sigma,
                        double *dD_out, double *dS_out)
 {
     const int nD = p->n_D, nS = p->n_sigma;
+    if (p->interp == 1) {
+        const double dD = p->D_max / (nD - 1);
+        double tD = D / dD;
+        int k = (int)floor(tD);
+        if (k > nD - 2) k = nD - 2;
+        if (k < 0) k = 0;
+        const double fD = tD - k;
+        double tS = sigma * (nS - 1);
+        int l = (int)floor(tS);
+        if (l > nS - 2) l = nS - 2;
+        if (l < 0) l = 0;
+        const double fS = tS - l;
+        double d0, d1;
+        const double c0 = vo_catmull_rom(vo_row(tab, nD, nS, k - 1, l), vo_row(tab, nD, nS, k, l),
+                                         vo_row(tab, nD, nS, k + 1, l), vo_row(tab, nD, nS, k + 2, l), fD, &d0);
+        const double c1 = vo_catmull_rom(vo_row(tab, nD, nS, k - 1, l + 1), vo_row(tab, nD, nS, k, l + 1),
+                                         vo_row(tab, nD, nS, k + 1, l + 1), vo_row(tab, nD, nS, k + 2, l + 1), fD,
+                                         &d1);
+        if (dD_out) *dD_out = ((1.0 - fS) * d0 + fS * d1) / dD;
+        if (dS_out) *dS_out = (c1 - c0) * (nS - 1);
+        return (1.0 - fS) * c0 + fS * c1;
+    }
     const double dD = p->D_max / (nD - 1);
     double tD = D / dD;
     int k = (int)floor(tD);
