@@ -97,7 +97,16 @@ typedef struct {
     int32_t graded_levels;  /* 0..40 */
     double  kappa;          /* > 0   */
     double  A0;             /* > 0   */
+    int32_t interp;         /* VDW_INTERP_BILINEAR (0) or VDW_INTERP_CUBIC_D (1):
+                               the pair and on-site terms read the table
+                               bilinearly, or cubic in D (Catmull-Rom form of
+                               each sigma column, rows beyond the ends
+                               extrapolated linearly; C1 in D) and linear in
+                               sigma.  The cubic form is offered with
+                               VDW_FP64 (VDW_FP32C gives VDW_EUNSUPPORTED). */
 } vdw_table_params;
+
+enum { VDW_INTERP_BILINEAR = 0, VDW_INTERP_CUBIC_D = 1 };
 
 /* Options of the energy / potential evaluation. */
 typedef struct {

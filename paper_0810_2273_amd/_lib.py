@@ -38,6 +38,7 @@ class VdwTableParams(ct.Structure):
     _fields_ = [
         ("n_D", ct.c_int32), ("n_sigma", ct.c_int32), ("D_max", ct.c_double),
         ("gl_points", ct.c_int32), ("graded_levels", ct.c_int32), ("kappa", ct.c_double), ("A0", ct.c_double),
+        ("interp", ct.c_int32),
     ]
 
 

@@ -28,10 +28,11 @@ class TableParams:
     graded_levels: int = 12
     kappa: float = 4.0
     A0: float = 64.0
+    interp: int = 0  # 0 bilinear, 1 cubic (C1) in D and linear in sigma (FP64 form)
 
     def c(self) -> L.VdwTableParams:
         return L.VdwTableParams(self.n_D, self.n_sigma, self.D_max, self.gl_points, self.graded_levels,
-                                self.kappa, self.A0)
+                                self.kappa, self.A0, self.interp)
 
 
 @dataclass

@@ -320,6 +320,7 @@ struct PairArgs {
     int JC;             // j-points per off-diagonal item (multiple of 64)
     int BI;             // i-points per row block (IPL x threads of the variant)
     int ND, DS;         // diagonal items per row block, each over a j sub-range of DS = BI / ND points
+    int interp;         // 1: cubic in D (FP64 form)
     double tDmax;       // n_D - 1: table branch iff t_D = D / dD < n_D - 1
     double tSclamp;     // largest value below n_sigma - 1 (sigma index clamp)
     double csig;        // sqrt(n_sigma - 1)
@@ -370,11 +371,16 @@ struct PairK {
     R m01, m02, m12;  // skew cells (see Seg)
     R en[9];
     int S, nS, K;
+    int nD;           // table rows
 };
 
 // Grid geometry of a pair-kernel variant: orthorhombic, cubic (equal
 // spacings), or skew (general metric).
 constexpr int kOrtho = 0, kCubic = 1, kSkew = 2;
+
+// The NSIG template value of the FP64 kernels that read the table cubic in D
+// (any n_sigma); NSIG = 0: any n_sigma, bilinear; NSIG > 0: that n_sigma.
+constexpr int kCubicD = -1;
 
 // min of two non-negative values; for FP32 an integer min on the bit
 // patterns (same order for non-negative floats, no NaN quieting needed)
@@ -447,14 +453,58 @@ __device__ __forceinline__ void asymptote(const PairK<R> &k, R m, R ai, R aj, R 
 //   t_D = (a_i + a_j) sqrt(m) = D / dD,  u = csig (a_i - a_j)/(a_i + a_j),  t_s = u^2 = sigma (n_sigma - 1)
 //   table branch: bilinear in (t_D, t_s);  beyond: -C' / (m^3 a_i^2 a_j^2 (a_i^2 + a_j^2)),  C' = C / (2 dD)^6
 // dqi, dqj are 2 dD / h_x times d phi~ / d q_i and d phi~ / d q_j.
+// Catmull-Rom cubic on [0, 1] between f[1] and f[2] (tangents (f[2]-f[0])/2,
+// (f[3]-f[1])/2) and its derivative in t.
+__device__ __forceinline__ double catmull_rom(const double (&f)[4], double t, double &dt)
+{
+    const double m1 = 0.5 * (f[2] - f[0]), m2 = 0.5 * (f[3] - f[1]);
+    const double t2 = t * t, t3 = t2 * t;
+    dt = (6.0 * t2 - 6.0 * t) * (f[1] - f[2]) + (3.0 * t2 - 4.0 * t + 1.0) * m1 + (3.0 * t2 - 2.0 * t) * m2;
+    return (2.0 * t3 - 3.0 * t2 + 1.0) * f[1] + (t3 - 2.0 * t2 + t) * m1 + (-2.0 * t3 + 3.0 * t2) * f[2] +
+           (t3 - t2) * m2;
+}
+
+// The C1 interpolant at cell (kk, l) with fractions (fD, fS): rows kk-1 ..
+// kk+2 of columns l and l+1 (from LDS when they are all held there, else
+// from the global table; beyond the table ends extrapolated linearly), the
+// cubic in D per column, then linear in sigma; gD, gS per unit t_D, t_s.
+template <int NSIG>
+__device__ __forceinline__ double cubic_d(const PairK<double> &k, const double *tab, const double *__restrict__ tabg,
+                                          int kk, int l, double fD, double fS, double &gD, double &gS)
+{
+    const int S = NSIG > 0 ? NSIG + 1 : k.S;
+    const int nS = NSIG > 0 ? NSIG : k.nS;
+    const bool lds = kk >= 1 && kk + 2 <= k.K - 1;
+    double c0[4], c1[4];
+    for (int i = 0; i < 4; ++i) {
+        const int rr = min(max(kk - 1 + i, 0), k.nD - 1);
+        const double *t = lds ? tab + (int64_t)rr * S + l : tabg + (int64_t)rr * nS + l;
+        c0[i] = t[0];
+        c1[i] = t[1];
+    }
+    if (kk == 0) {
+        c0[0] = 2.0 * c0[1] - c0[2];
+        c1[0] = 2.0 * c1[1] - c1[2];
+    }
+    if (kk + 2 > k.nD - 1) {
+        c0[3] = 2.0 * c0[2] - c0[1];
+        c1[3] = 2.0 * c1[2] - c1[1];
+    }
+    double d0, d1;
+    const double v0 = catmull_rom(c0, fD, d0), v1 = catmull_rom(c1, fD, d1);
+    gD = d0 + fS * (d1 - d0);
+    gS = v1 - v0;
+    return v0 + fS * (v1 - v0);
+}
+
 // FP64 form: ci = b_i = csig a_i and cj = csig a_j, u = (b_i - csig a_j) / s.
 template <bool ADJ, bool JSIDE, int NSIG>
 __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *tab, const double *__restrict__ tabg,
                                           double m, double ai, double ci, double aj, double cj, double &phi,
                                           double &dqi, double &dqj)
 {
-    const int S = NSIG ? NSIG + 1 : k.S;
-    const int nS = NSIG ? NSIG : k.nS;
+    const int S = NSIG > 0 ? NSIG + 1 : k.S;
+    const int nS = NSIG > 0 ? NSIG : k.nS;
     const double r = dsqrt(m);
     const double s = ai + aj;
     const double tD = s * r;
@@ -465,6 +515,17 @@ __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *
         const int kk = (int)tD;
         const int l = (int)ts;
         const double fD = dfract(tD), fS = dfract(ts);
+        if constexpr (NSIG == kCubicD) {
+            double gD, gS;
+            phi = cubic_d<NSIG>(k, tab, tabg, kk, l, fD, fS, gD, gS);
+            if (ADJ) {
+                const double X = gD * r;
+                const double Y = (gS * (u * inv)) * (inv * k.c4);
+                dqi = X + Y * aj;
+                if (JSIDE) dqj = X - Y * ai;
+            }
+            return;
+        }
         // rows below K come from LDS; the clamped LDS read is always in
         // bounds and is replaced for rows >= K - 1
         const int kl = min(kk, k.K - 2);
@@ -496,8 +557,8 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
                                           float &dqj)
 {
     (void)cj;
-    const int S = NSIG ? NSIG + 1 : k.S;
-    const int nS = NSIG ? NSIG : k.nS;
+    const int S = NSIG > 0 ? NSIG + 1 : k.S;
+    const int nS = NSIG > 0 ? NSIG : k.nS;
     const float r = dsqrt(m);
     const float s = ai + aj;
     const float tD = s * r;
@@ -734,6 +795,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
     kc.S = A.S;
     kc.nS = nS;
     kc.K = A.K;
+    kc.nD = A.nD;
 
     for (int t = threadIdx.x; t < A.K * nS; t += TPB) {
         int r = t / nS, c = t - r * nS;
@@ -998,6 +1060,7 @@ struct FinArgs {
     int JC, BI, ND, NI, NJ;
     int img, adj, self_term;
     int vg;                   // voxel term: Gauss-Legendre points per octant axis
+    int interp;               // 1: the table is read cubic in D
     double vu[kVoxelGL], vw[kVoxelGL];  // voxel term: nodes u in (0, 1) and weights 2 u w (1 - u^2)
     const int32_t *gidx;
     const double *n, *q0, *dqdn;
@@ -1021,6 +1084,17 @@ __device__ inline double self_phi(const FinArgs &F, double D, double *dphi)
     int k = (int)floor(tD);
     if (k > F.nD - 2) k = F.nD - 2;
     double fD = tD - k;
+    if (F.interp == VDW_INTERP_CUBIC_D) {
+        // column sigma = 0, rows k-1 .. k+2 (extrapolated linearly beyond the ends)
+        double c[4];
+        for (int i = 0; i < 4; ++i) c[i] = F.tab[(int64_t)min(max(k - 1 + i, 0), F.nD - 1) * F.nS];
+        if (k == 0) c[0] = 2.0 * c[1] - c[2];
+        if (k + 2 > F.nD - 1) c[3] = 2.0 * c[2] - c[1];
+        double dt;
+        const double v = catmull_rom(c, fD, dt);
+        *dphi = dt / F.dD;
+        return v;
+    }
     double p0 = F.tab[(int64_t)k * F.nS], p1 = F.tab[(int64_t)(k + 1) * F.nS];
     *dphi = (p1 - p0) / F.dD;
     return p0 + fD * (p1 - p0);
@@ -1599,13 +1673,19 @@ int launch_pair_v(int adj, int img, int tpb, const PairArgs &a, const PairPtrs &
 int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tpb, const PairArgs &a,
                 const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
+    const bool cubd = a.interp == VDW_INTERP_CUBIC_D;
+    if (cubd && !fp64) return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is offered with VDW_FP64 only");
     if (geo == kSkew) {
         if (kahan) return fail(VDW_EUNSUPPORTED, "kahan = 1 is not available on skew cells");
-        if (fp64) return launch_pair_v<double, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        if (fp64)
+            return cubd ? launch_pair_v<double, false, kCubicD, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                        : launch_pair_v<double, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
         if (nsig == 64) return launch_pair_v<float, false, 64, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
         return launch_pair_v<float, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     }
-    if (fp64) return launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (fp64)
+        return cubd ? launch_pair_v<double, false, kCubicD, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                    : launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (kahan) return launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (nsig == 64)
         return geo == kCubic ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
@@ -1617,7 +1697,7 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
 // work layout, the launch shapes and the constant kernel arguments.
 struct Exec {
     Plan P;
-    int B = 0, adj = 0, fp64 = 0, kahan = 0, nsig = 0, geo = kCubic, self_term = 0;
+    int B = 0, adj = 0, fp64 = 0, kahan = 0, nsig = 0, geo = kCubic, self_term = 0, interp = 0;
     int tpb = 1024;  // pair-kernel workgroup size
     int K = 0, grid = 0;
     size_t lds = 0;
@@ -1638,6 +1718,8 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     if (rc) return rc;
     rc = validate_table(tp);
     if (rc) return rc;
+    if (tp->interp == VDW_INTERP_CUBIC_D && o->precision != VDW_FP64)
+        return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is offered with VDW_FP64 only");
     if (B < 1) return fail(VDW_EINVAL, "B must be >= 1");
     if (!grids) return fail(VDW_EINVAL, "NULL argument");
     if (!ws) return fail(VDW_EINVAL, "workspace is NULL");
@@ -1650,6 +1732,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     E->kahan = o->kahan;
     E->nsig = tp->n_sigma;
     E->self_term = o->self_term;
+    E->interp = tp->interp;
     E->n_cut = o->n_cut;
     rc = make_plan(B, grids, grid_off, o, tp->n_sigma, E->fp64, adj, &E->P);
     if (rc) return rc;
@@ -1685,6 +1768,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     pa.JC = P.JC;
     pa.BI = P.BI;
     pa.ND = P.ND;
+    pa.interp = tp->interp;
     pa.DS = P.BI / P.ND;
     pa.csig = sqrt((double)(tp->n_sigma - 1));
     pa.tDmax = (double)(tp->n_D - 1);
@@ -1820,6 +1904,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.adj = E.adj;
     fa.self_term = E.self_term;
     fa.vg = kVoxelGL;
+    fa.interp = E.interp;
     voxel_rule(fa.vu, fa.vw);
     fa.gidx = gidx;
     fa.n = n_d;

@@ -105,6 +105,8 @@ int validate_table(const vdw_table_params *tp)
     if (tp->graded_levels < 0 || tp->graded_levels > 40) return fail(VDW_EINVAL, "graded_levels must be in 0..40");
     if (!(tp->kappa > 0.0) || !(tp->A0 > 0.0) || !isfinite(tp->kappa) || !isfinite(tp->A0))
         return fail(VDW_EINVAL, "kappa and A0 must be > 0");
+    if (tp->interp != VDW_INTERP_BILINEAR && tp->interp != VDW_INTERP_CUBIC_D)
+        return fail(VDW_EINVAL, "interp must be VDW_INTERP_BILINEAR or VDW_INTERP_CUBIC_D");
     return VDW_OK;
 }
 
