@@ -144,6 +144,42 @@ def test_kr_dimer_adjoint_vs_finite_differences(V, oracle, big):
     assert np.all(np.abs(gv - fd) <= 1e-2 * np.abs(fd))
 
 
+def test_kr_dimer_adjoint_vs_finite_differences_cubic_table(V, oracle, big):
+    """The same check at 32 kept points with the C1 interpolant (cubic in D,
+    FP64) and with the bilinear one: the GPU equals the exact adjoint of its
+    interpolant in both (1e-10), and removing the D kinks brings central
+    differences closer to it (the sigma kinks and the switch at D_max
+    remain)."""
+    import torch
+
+    tp0, tab = big
+    wl = W.kr_dimer(7.0)
+    rho = wl.rho.reshape(-1)
+    g = oracle.Grid(wl.n, wl.h, wl.periodic)
+    ops = oracle.gradient_operators(g)
+    rng = np.random.default_rng(65)
+    ks = np.array(rng.choice(np.flatnonzero(rho >= wl.n_cut), 32, replace=False))
+    t64 = torch.tensor(tab, dtype=torch.float64, device="cuda:0").contiguous()
+    l2 = {}
+    for interp in (0, 1):
+        tp = oracle.table_params(n_D=tp0.n_D, n_sigma=tp0.n_sigma, D_max=tp0.D_max, gl_points=tp0.gl_points,
+                                 graded_levels=tp0.graded_levels, kappa=tp0.kappa, A0=tp0.A0, interp=interp)
+        params = V.TableParams(n_D=tp.n_D, n_sigma=tp.n_sigma, D_max=tp.D_max, gl_points=tp.gl_points,
+                               graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0, interp=interp)
+        _, v = _kr_potential(V, wl, V.Table(params, t64, t64.float().contiguous()), 0)
+        fd = np.empty(len(ks))
+        for t, k in enumerate(ks):
+            eps = 1e-4 * rho[k]
+            fd[t] = oracle.local_energy_change(g, wl.rho, k, eps, tab, tp, wl.n_cut, ops=ops) / (2 * eps)
+        ref = oracle.potential_at(g, wl.rho, ks, tab, tp, wl.n_cut)
+        gv = v[ks]
+        l2[interp] = np.linalg.norm(gv - fd) / np.linalg.norm(fd)
+        say(f"  interp {interp}: GPU vs exact adjoint {np.linalg.norm(gv - ref) / np.linalg.norm(ref):.3e}; "
+            f"GPU vs FD: max per point {np.max(np.abs(gv - fd) / np.abs(fd)):.3e}, L2 {l2[interp]:.3e}")
+        assert np.linalg.norm(gv - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert l2[1] < l2[0]
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec,vtol", [(0, 1e-10), (1, 1e-4)])
 def test_kr_dimer_potential_on_24_cubed_subgrid(V, oracle, big, prec, vtol):
