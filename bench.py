@@ -47,7 +47,7 @@ PROFILE_COUNTERS = {
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
-TRAFFIC_BYTES = {"kr": (5055168.3125 * 2.0 + 6034241.21875) * 1024}
+TRAFFIC_BYTES = {"kr": (5047278.3125 * 2.0 + 6034241.21875) * 1024}
 
 
 def parse():
