@@ -45,7 +45,7 @@ enum {
     VDW_EINVAL = -1,        /* bad argument: null pointer, size, parameter range  */
     VDW_ENOMEM = -2,        /* host allocation failed (batch plan object)         */
     VDW_EHIP = -3,          /* a HIP runtime call failed                          */
-    VDW_EUNSUPPORTED = -4,  /* valid but not implemented (Kahan runs on a skew cell) */
+    VDW_EUNSUPPORTED = -4,  /* valid but not offered (e.g. the cubic-in-D table in FP32C) */
     VDW_EWORKSPACE = -5,    /* workspace smaller than enl_workspace_size()        */
     VDW_ENONFINITE = -6     /* NaN or Inf found in the density                    */
 };
@@ -137,8 +137,7 @@ typedef struct {
                                shorter than a row block split its diagonal
                                work into (block / chunk) items.               */
     int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
-    int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only;
-                               not on skew cells)                             */
+    int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only)     */
 } vdw_opts;
 
 /* Thread-local description of the last error (never NULL). */
@@ -245,8 +244,8 @@ size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, cons
  *   phi_f:     device FP32 table (required for VDW_FP32C, else ignored).
  *   ws, ws_bytes: device workspace of at least enl_workspace_size() bytes.
  *   E_out:     host, 3 doubles: {E_pair0, E_pairL, E_self} (Hartree).
- * Errors: VDW_EINVAL, VDW_EUNSUPPORTED (kahan = 1 on a skew cell),
- * VDW_EWORKSPACE, VDW_EHIP.
+ * Errors: VDW_EINVAL, VDW_EUNSUPPORTED (the cubic-in-D table with
+ * VDW_FP32C), VDW_EWORKSPACE, VDW_EHIP.
  * ------------------------------------------------------------------- */
 int enl_energy(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *phi_d,
                const float *phi_f, const vdw_table_params *tp, const vdw_opts *opts, void *ws,

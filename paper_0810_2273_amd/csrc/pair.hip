@@ -1479,7 +1479,6 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             if (grids[0].periodic[a] && o->image_max[a] > 0) nimg *= 2 * o->image_max[a] + 1;
         const bool img = nimg > 1 || o->r_cut > 0.0;
         const bool fast = !fp64 && !o->kahan && nsig == 64;
-        if (P->skew && o->kahan) return fail(VDW_EUNSUPPORTED, "kahan = 1 is not available on skew cells");
         // workgroup shape: 512 threads with eight i-points per lane on request
         // (FP32 n_sigma = 64 kernels without images); 256 threads with two on
         // request or, by default, when even the finest chunking of the
@@ -1641,8 +1640,9 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 // threads); each with and without the adjoint sums and the image loop.
 // Without images every one of them also has 256-thread workgroups with two
 // i-points per lane, for work lists too short to occupy every CU.  Skew
-// cells (FP64, FP32C with n_sigma = 64 or any) have two i-points per lane in
-// 1024-thread workgroups, with and without the adjoint and the image loop.
+// cells (FP64, FP32C with n_sigma = 64 or any, Kahan-compensated FP32C) have
+// two i-points per lane in 1024-thread workgroups, with and without the
+// adjoint and the image loop.
 template <typename R, bool KAHAN, int NSIG, int GEO>
 int launch_pair_v(int adj, int img, int tpb, const PairArgs &a, const PairPtrs &p, int grid, size_t lds,
                   hipStream_t s, bool attr_only)
@@ -1676,7 +1676,7 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
     const bool cubd = a.interp == VDW_INTERP_CUBIC_D;
     if (cubd && !fp64) return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is offered with VDW_FP64 only");
     if (geo == kSkew) {
-        if (kahan) return fail(VDW_EUNSUPPORTED, "kahan = 1 is not available on skew cells");
+        if (kahan) return launch_pair_v<float, true, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
         if (fp64)
             return cubd ? launch_pair_v<double, false, kCubicD, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only)
                         : launch_pair_v<double, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);

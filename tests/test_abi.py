@@ -89,15 +89,14 @@ def test_host_side_validation(L):
     assert lib.enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)) > 0
     o.j_chunks = 99
     assert lib.enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)) == 0
-    # skew cells are planned (general-metric kernels), except with Kahan runs
+    # skew cells are planned (general-metric kernels), Kahan runs included
     o.j_chunks = 0
     skew = L.VdwGrid.from_buffer_copy(g)
     skew.cell[1][0] = 1.5
     assert lib.enl_workspace_size(ct.byref(skew), ct.byref(tp), ct.byref(o)) > 0
     o.kahan = 1
     o.precision = 1
-    assert lib.enl_workspace_size(ct.byref(skew), ct.byref(tp), ct.byref(o)) == 0
-    assert b"skew" in lib.vdw_last_error()
+    assert lib.enl_workspace_size(ct.byref(skew), ct.byref(tp), ct.byref(o)) > 0
 
 
 def test_batch_plan_host_validation(L):
