@@ -10,9 +10,12 @@
  *     of Dion et al. (their Eq. 14), with their large-D asymptote (Eq. 17).
  *   - Sec. 2, Eq. (2): on the density grid the integral is the double sum
  *     E = 1/2 sum_i sum_j n_i phi_ij n_j (times dV^2, the volume elements).
- *   - Sec. 3: the gradient of n by finite differences (perpendicular axes),
- *     a density cut-off below which points are dropped, the sum over the
- *     0th cell, then over periodic repetitions of it.
+ *   - Sec. 3: the gradient of n (finite differences, or the Fourier
+ *     derivative the paper's code takes by FFT), a density cut-off below
+ *     which points are dropped, the sum over the 0th cell, then over
+ *     periodic repetitions of it.
+ *   - Eq. (3): the recombination with the LDA and GGA exchange-correlation
+ *     energies, which the paper's code also evaluates.
  *
  * Conventions for every entry point:
  *   - Units are Hartree atomic units (bohr, Hartree, electrons/bohr^3).
@@ -161,16 +164,21 @@ const char *vdw_version(void);
 int build_phi_table(const vdw_table_params *tp, double *phi_d, float *phi_f, void *stream);
 
 /* ---------------------------------------------------------------------
- * compute_q0 -- density gradient and q0 on every grid point (Sec. 3: FD
- * gradient on perpendicular axes; q0 of Dion et al. from the LDA exchange
- * and Perdew-Wang 1992 correlation plus the gradient term):
- *   grad_a n: second-order central differences, periodic wrap on periodic
- *             axes, second-order one-sided differences at the faces of
- *             non-periodic axes;
+ * compute_q0 -- density gradient and q0 on every grid point (Sec. 3; q0 of
+ * Dion et al. from the LDA exchange and Perdew-Wang 1992 correlation plus
+ * the gradient term):
+ *   grad n:  along each grid axis second-order central differences with
+ *            periodic wrap on periodic axes and second-order one-sided
+ *            differences at the faces of non-periodic axes, or the Fourier
+ *            derivative on periodic axes (grid->gradient); divided by the
+ *            spacing on orthorhombic cells, mapped by the inverse step
+ *            matrix on skew cells (Cartesian components);
  *   q0 = k_F - (4 pi/3) eps_c^PW92(r_s) - (Z_ab/36) |grad n|^2 / (k_F n^2),
  *        Z_ab = -0.8491, where n >= n_cut; 0 elsewhere.
  *   n_d:     device, G doubles (read).
- *   grad_d:  device, 3G doubles (planes d/dx, d/dy, d/dz), or NULL.
+ *   grad_d:  device, 3G doubles (planes d/dx, d/dy, d/dz), or NULL (not
+ *            with the spectral gradient, which stages its derivatives
+ *            there).
  *   q0_d:    device, G doubles (written).
  *   dq_dn_d: device, G doubles, or NULL: dq0/dn at fixed |grad n|^2.
  *   dq_dg_d: device, G doubles, or NULL: dq0/d(|grad n|^2).

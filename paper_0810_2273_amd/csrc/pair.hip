@@ -1,7 +1,8 @@
 // The O(N^2) double sum of Eq. (2) (paper, Sec. 2) over the points kept by
 // the density cut-off (Sec. 3), with periodic images of the 0th cell
-// (Sec. 3), the on-site term, the deterministic FP64 reductions, and the
-// adjoint dE/dn through q0 and the finite-difference gradient.
+// (Sec. 3), the on-site term (sphere or cell average), the deterministic
+// FP64 reductions, and the adjoint dE/dn through q0 and the gradient, on
+// orthorhombic or skew cells.
 //
 // Pipeline of one call (all on the caller's stream, no host round trip
 // before the final copy of the energies):
@@ -15,11 +16,12 @@
 //   pair      persistent workgroups (one per CU) pull work items from an
 //             atomic counter.  The kept points of a density are cut into
 //             row blocks of IPL x (workgroup size) points, IPL i-points per
-//             lane (four for the FP32 n_sigma = 64 kernels without images,
-//             two elsewhere).  Row block I owns one diagonal item (ordered
-//             pairs inside the block, j records streamed through scalar
-//             registers) and items (I, c) pairing it with chunks of the
-//             points after the block.  Off-diagonal pairs are evaluated once
+//             lane (four for the FP32 n_sigma = 64 kernels without images in
+//             1024-thread workgroups, eight in 512-thread ones, two
+//             elsewhere).  Row block I owns ND diagonal items (ordered pairs
+//             of the block's points with one of ND j sub-ranges of it, j
+//             records streamed through scalar registers) and items (I, c)
+//             pairing it with chunks of the points after the block.  Off-diagonal pairs are evaluated once
 //             for both orders: each wavefront loads a 64-record j tile into
 //             its lanes and rotates it one lane per step (DPP wave rotate),
 //             carrying the j-side sums with the records, so after 64 steps
@@ -31,7 +33,8 @@
 //   finalize  per point: fixed-order sum of its item partials, on-site term,
 //             energy terms, and (potential) the direct part of dE/dn
 //   reduce    per density: fixed-order sum of the block partials
-//   assemble  (potential) transposed gradient stencil on the whole grid
+//   assemble  (potential) transposed gradient stencil on the whole grid (the
+//             axes with the Fourier derivative follow as line kernels)
 #include <math.h>
 #include <string.h>
 

@@ -1,8 +1,10 @@
 // Gradient and q0 of one grid point, shared by the single-grid kernel, the
 // batched one and the exchange-correlation energies: second-order finite
-// differences on perpendicular axes (Sec. 3), q0 of Dion et al. from the LDA
-// exchange, the Perdew-Wang 1992 correlation (its logarithm as log1p) and
-// the gradient term; FP64.
+// differences along the grid axes (Sec. 3; or Fourier derivatives computed
+// before), Cartesian components through the spacing or, on skew cells, the
+// inverse step matrix; q0 of Dion et al. from the LDA exchange, the
+// Perdew-Wang 1992 correlation (its logarithm as log1p) and the gradient
+// term; FP64.
 #pragma once
 
 #include <math.h>
