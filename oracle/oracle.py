@@ -3,12 +3,14 @@
 Plain FP64 CPU reference of everything the GPU library computes.  It is
 written from the mathematics of Lazic et al. (arXiv:0810.2273), Sec. 2
 (Eqs. 1-2, the kernel of Dion et al. and its large-D asymptote), Sec. 3
-(gradient, density cut-off, 0th cell plus periodic repetition), and from
-the published ingredients that paper builds on: the Dion et al. q0
-(LDA exchange-correlation plus gradient term), the Perdew-Wang 1992 LDA
+(gradient, density cut-off, 0th cell plus periodic repetition), Sec. 7
+(the large-D form of the kernel for the far repeated cells), and from the
+published ingredients that paper builds on: the Dion et al. q0 (LDA
+exchange-correlation plus gradient term), the Perdew-Wang 1992 LDA
 correlation, and the PBE and revPBE exchange and PBE correlation energies
-that enter the recombination of Eq. (3).  The heavy loops (quadrature of the kernel, the double
-sum) live in vdw_oracle.c; the O(grid) steps are numpy/scipy here.
+that enter the recombination of Eq. (3).  The heavy loops (quadrature of
+the kernel, the double sum) live in vdw_oracle.c; the O(grid) steps are
+numpy/scipy here.
 
 Only tests/, the smoke check and the benchmark's CPU-baseline leg may use
 this module.  It shares no code with the HIP library and does not import
@@ -108,6 +110,13 @@ def lib():
     L.vo_pair_rows_cell.argtypes = L.vo_pair_rows.argtypes
     L.vo_block_sum_cell.restype = d
     L.vo_block_sum_cell.argtypes = L.vo_block_sum.argtypes
+    L.vo_far_T.restype = d
+    L.vo_far_T.argtypes = [dp, P(i32), P(i32), P(i32), P(i32), d, d, d]
+    L.vo_far_rows.restype = ct.c_int
+    L.vo_far_rows.argtypes = [
+        ct.c_long, P(i32), P(i32), P(i32), dp, dp,
+        dp, P(i32), P(i32), P(i32), P(i32), ct.c_long, P(i64), dp, dp,
+    ]
     L.vo_num_threads.restype = ct.c_int
     _lib = L
     return L
@@ -625,6 +634,66 @@ def block_sum(grid: Grid, A, B, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), 
         _p(tab, ct.c_double), ct.byref(tp)))
 
 
+def far_on(grid: Grid, far_max) -> bool:
+    """True when far_max selects a far image shell on some periodic axis."""
+    return far_max is not None and any(p and f > 0 for p, f in zip(grid.periodic, far_max))
+
+
+def check_far(grid: Grid, image_max, far_max, r_cut):
+    """The far shell needs no distance cut and far_max >= image_max on every
+    periodic axis."""
+    if not far_on(grid, far_max):
+        return
+    if r_cut > 0.0:
+        raise ValueError("the far image shell is defined without a distance cut")
+    for p, m, f in zip(grid.periodic, image_max, far_max):
+        if p and f < m:
+            raise ValueError("far_max must be >= image_max on every periodic axis")
+
+
+def far_T(grid: Grid, image_max, far_max, d):
+    """T(d) = sum over the far shell of |d - L|^-6 (bohr^-6) for grid
+    displacements d (rows of integer steps along the three axes)."""
+    E = np.ascontiguousarray(grid.steps.ravel())
+    gd = np.asarray(grid.n, dtype=np.int32)
+    per = np.asarray(grid.periodic, dtype=np.int32)
+    im = np.asarray(image_max, dtype=np.int32)
+    fm = np.asarray(far_max, dtype=np.int32)
+    d = np.atleast_2d(np.asarray(d, dtype=np.float64))
+    return np.array([lib().vo_far_T(_p(E, ct.c_double), _p(gd, ct.c_int32), _p(per, ct.c_int32),
+                                    _p(im, ct.c_int32), _p(fm, ct.c_int32), *map(float, row)) for row in d])
+
+
+def far_rows(grid: Grid, ix, iy, iz, n, q, image_max, far_max, rows=None):
+    """Per-row sums of the far image shell (the kernel's large-D asymptote
+    summed over the images beyond image_max up to far_max, the pair i = j
+    included): F0_i = sum_j n_j phi_far(i, j), Fq_i = sum_j n_j d phi_far / d q_i."""
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    iz = np.ascontiguousarray(iz, dtype=np.int32)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    E = np.ascontiguousarray(grid.steps.ravel())
+    gd = np.asarray(grid.n, dtype=np.int32)
+    per = np.asarray(grid.periodic, dtype=np.int32)
+    im = np.asarray(image_max, dtype=np.int32)
+    fm = np.asarray(far_max, dtype=np.int32)
+    if rows is None:
+        nrows, rows_p = len(n), None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        nrows, rows_p = len(rows), _p(rows, ct.c_int64)
+    F0 = np.zeros(nrows)
+    Fq = np.zeros(nrows)
+    rc = lib().vo_far_rows(len(n), _p(ix, ct.c_int32), _p(iy, ct.c_int32), _p(iz, ct.c_int32), _p(n, ct.c_double),
+                           _p(q, ct.c_double), _p(E, ct.c_double), _p(gd, ct.c_int32), _p(per, ct.c_int32),
+                           _p(im, ct.c_int32), _p(fm, ct.c_int32), nrows, rows_p, _p(F0, ct.c_double),
+                           _p(Fq, ct.c_double))
+    if rc:
+        raise MemoryError("far_rows: table allocation failed")
+    return F0, Fq
+
+
 @dataclass
 class Result:
     E_pair0: float
@@ -640,9 +709,12 @@ class Result:
         return self.E_pair0 + self.E_pairL + self.E_self
 
 
-def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True, potential=False):
+def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True, potential=False,
+             far_max=None):
     """E_c^nl = 1/2 dV^2 sum_{(i,j,L) != (i,i,0)} n_i n_j phi~ (Eq. 2 with the volume
-    element written out) + E_self, and optionally dE/dn at every grid point."""
+    element written out) + E_self, and optionally dE/dn at every grid point.
+    With far_max the far image shell (see far_rows) joins the image sums."""
+    check_far(grid, image_max, far_max, r_cut)
     r = np.asarray(rho, dtype=np.float64).reshape(-1)
     qd = compute_q0(grid, r, n_cut)
     keep = qd["keep"]
@@ -651,6 +723,10 @@ def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, se
     qS = qd["q0"][idx]
     dV = grid.dV
     S0c, S0i, Sq = pair_rows(grid, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut)
+    if far_on(grid, far_max):
+        F0, Fq = far_rows(grid, ix, iy, iz, nS, qS, image_max, far_max)
+        S0i = S0i + F0
+        Sq = Sq + Fq
     E0 = 0.5 * dV * dV * float(np.sum(nS * S0c))
     EL = 0.5 * dV * dV * float(np.sum(nS * S0i))
     Phi = np.zeros(len(nS))
@@ -735,11 +811,13 @@ def local_energy_change(grid: Grid, rho, k, eps, tab, tp, n_cut, image_max=(0, 0
     return part(rp) - part(rm)
 
 
-def potential_at(grid: Grid, rho, ks, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True):
+def potential_at(grid: Grid, rho, ks, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, self_term=True,
+                 far_max=None):
     """dE/dn_k at the grid points ks only: the rows of the double sum that
     the formula of `adjoint` needs at k (k itself and the kept points whose
     gradient stencil contains k) are summed over every j, nothing else.
     Same arithmetic as `evaluate(..., potential=True)` restricted to ks."""
+    check_far(grid, image_max, far_max, r_cut)
     r = np.asarray(rho, dtype=np.float64).reshape(-1)
     qd = compute_q0(grid, r, n_cut)
     keep = qd["keep"]
@@ -759,6 +837,10 @@ def potential_at(grid: Grid, rho, ks, tab, tp, n_cut, image_max=(0, 0, 0), r_cut
     nS, qS = r[idx], qd["q0"][idx]
     if len(rows):
         S0c, S0i, Sq = pair_rows(grid, ix, iy, iz, nS, qS, tab, tp, image_max, r_cut, rows=rows)
+        if far_on(grid, far_max):
+            F0, Fq = far_rows(grid, ix, iy, iz, nS, qS, image_max, far_max, rows=rows)
+            S0i = S0i + F0
+            Sq = Sq + Fq
     else:
         S0c = S0i = Sq = np.zeros(0)
     dV = grid.dV

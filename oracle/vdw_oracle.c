@@ -14,7 +14,8 @@
  *     et al. (their Eq. 17, named in Sec. 2) beyond the table;
  *   - the discrete double sum of Eq. (2), with periodic images of the
  *     0th cell (Sec. 3, periodic problems; Sec. 6.2);
- *   - the per-point sums the adjoint needs (derivative of Eq. (2)).
+ *   - the per-point sums the adjoint needs (derivative of Eq. (2));
+ *   - the far image shell with the large-D asymptote (Sec. 7 outlook).
  *
  * Only tests/, the smoke check and the benchmark's CPU-baseline leg may
  * load this code.  It shares nothing with the HIP library: no headers,
@@ -625,6 +626,80 @@ double vo_block_sum_cell(long na, const int32_t *ia, long nb, const int32_t *ib,
     for (long s = 0; s < na; ++s) total += part[s];
     free(part);
     return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* Far image shell.  The paper's outlook (Sec. 7) is to use the large-D */
+/* form of the kernel to speed up the sum over repeated cells.  Here    */
+/* the images L = sum_a m_a n_a e_a with |m_a| <= far_max[a] on the      */
+/* periodic axes, except those with every |m_a| <= image_max[a] (the    */
+/* near images, summed with the table), enter with the asymptote of     */
+/* Dion et al. (their Eq. 17) whatever D.  Summed over the shell, the   */
+/* ordered pair (i, j) -- i = j included: a point meets its own far      */
+/* images -- then contributes                                           */
+/*   phi_far(i, j) = -C T(r_i - r_j) / (q_i^2 q_j^2 (q_i^2 + q_j^2)),    */
+/*   T(d) = sum over the shell of |d - L|^-6,                           */
+/* and d phi_far / d q_i = -phi_far (2 / q_i + 2 q_i / (q_i^2 + q_j^2)).  */
+/* ------------------------------------------------------------------ */
+double vo_far_T(const double E[9], const int32_t gdim[3], const int32_t periodic[3],
+                const int32_t image_max[3], const int32_t far_max[3],
+                double d0, double d1, double d2)
+{
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = periodic[a] ? image_max[a] : 0;
+        hi[a] = periodic[a] ? far_max[a] : 0;
+    }
+    double s = 0.0;
+    for (int a = -hi[0]; a <= hi[0]; ++a)
+        for (int b = -hi[1]; b <= hi[1]; ++b)
+            for (int c = -hi[2]; c <= hi[2]; ++c) {
+                if (abs(a) <= lo[0] && abs(b) <= lo[1] && abs(c) <= lo[2]) continue;
+                double r = vo_cell_dist(E, d0 - (double)a * gdim[0], d1 - (double)b * gdim[1],
+                                        d2 - (double)c * gdim[2]);
+                s += 1.0 / (r * r * r * r * r * r);
+            }
+    return s;
+}
+
+/* Per-row sums of the far shell: F0_i = sum_j n_j phi_far(i, j) and      */
+/* Fq_i = sum_j n_j d phi_far(i, j) / d q_i, over every kept j (rows as   */
+/* in vo_pair_rows).  T is tabulated first over all grid displacements.  */
+int vo_far_rows(long npts, const int32_t *ix, const int32_t *iy, const int32_t *iz,
+                const double *n, const double *q,
+                const double E[9], const int32_t gdim[3], const int32_t periodic[3],
+                const int32_t image_max[3], const int32_t far_max[3],
+                long nrows, const int64_t *rows, double *F0, double *Fq)
+{
+    const long ex = 2L * gdim[0] - 1, ey = 2L * gdim[1] - 1, ez = 2L * gdim[2] - 1;
+    const long ne = ex * ey * ez;
+    double *T = (double *)malloc(sizeof(double) * (size_t)ne);
+    if (!T) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long e = 0; e < ne; ++e) {
+        long d0 = e % ex, rest = e / ex;
+        long d1 = rest % ey, d2 = rest / ey;
+        T[e] = vo_far_T(E, gdim, periodic, image_max, far_max, (double)(d0 - (gdim[0] - 1)),
+                        (double)(d1 - (gdim[1] - 1)), (double)(d2 - (gdim[2] - 1)));
+    }
+    const double C = vo_asym_C();
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long t = 0; t < nrows; ++t) {
+        long i = rows ? (long)rows[t] : t;
+        double f0 = 0.0, fq = 0.0;
+        double qi2 = q[i] * q[i];
+        for (long j = 0; j < npts; ++j) {
+            long e = (ix[i] - ix[j] + gdim[0] - 1) + ex * ((iy[i] - iy[j] + gdim[1] - 1) + ey * (long)(iz[i] - iz[j] + gdim[2] - 1));
+            double qj2 = q[j] * q[j];
+            double ph = -C * T[e] / (qi2 * qj2 * (qi2 + qj2));
+            f0 += n[j] * ph;
+            fq += n[j] * (-ph) * (2.0 / q[i] + 2.0 * q[i] / (qi2 + qj2));
+        }
+        F0[t] = f0;
+        Fq[t] = fq;
+    }
+    free(T);
+    return 0;
 }
 
 int vo_num_threads(void)
