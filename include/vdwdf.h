@@ -141,6 +141,16 @@ typedef struct {
                                work into (block / chunk) items.               */
     int32_t grid_blocks;    /* persistent workgroups; 0: auto (all CUs)           */
     int32_t kahan;          /* 1: Kahan-compensate the FP32 runs (FP32C only)     */
+    int32_t far_max[3];     /* far image shell (Sec. 7: the large-D form of the
+                               kernel for the far repeated cells): the images
+                               with |m_a| <= far_max[a] on periodic axes that
+                               are not near images (image_max) enter with the
+                               asymptote -C/(d1^2 d2^2 (d1^2 + d2^2)) whatever
+                               D; all 0 (or 0 on every periodic axis): none.
+                               With a shell: r_cut <= 0, far_max[a] >=
+                               image_max[a] on every periodic axis, at most
+                               2^22 lattice vectors, one density per call
+                               (B > 1 gives VDW_EUNSUPPORTED).                */
 } vdw_opts;
 
 /* Thread-local description of the last error (never NULL). */
@@ -244,7 +254,12 @@ size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, cons
  *     0: none.
  * L runs over the images selected by opts->image_max on periodic axes
  * (Sec. 3, periodic problems), and every (i, j, L) with a distance above
- * opts->r_cut (if > 0) is dropped.  dV = |det(cell)| / G (hx hy hz on
+ * opts->r_cut (if > 0) is dropped.  With a far image shell
+ * (opts->far_max) E_pairL also holds
+ *   1/2 dV^2 sum_{i, j in S} n_i n_j (-C) T(r_i - r_j) / (q_i^2 q_j^2 (q_i^2 + q_j^2)),
+ *   T(d) = sum_{L in shell} |d - L|^-6  (i = j included),
+ * the asymptote summed over the shell's images (one O(N^2) pass over a
+ * table of T at every grid displacement, whatever the shell's size).  dV = |det(cell)| / G (hx hy hz on
  * orthorhombic cells).
  *   n_d, q0_d: device, G doubles (q0 from compute_q0).
  *   phi_d:     device FP64 table (always required: the on-site term and the
@@ -364,6 +379,7 @@ typedef struct {
     int32_t j_chunks;
     int32_t grid_blocks;
     int32_t diag_items;     /* diagonal work items per row block */
+    double  far_pairs;      /* ordered pairs (i, j) of the far-shell pass (N^2), or 0 */
 } vdw_stats;
 
 int vdw_last_stats(vdw_stats *out);

@@ -47,6 +47,7 @@ class VdwOpts(ct.Structure):
         ("n_cut", ct.c_double), ("r_cut", ct.c_double), ("image_max", ct.c_int32 * 3),
         ("precision", ct.c_int32), ("self_term", ct.c_int32), ("table_lds_rows", ct.c_int32),
         ("block_threads", ct.c_int32), ("j_chunks", ct.c_int32), ("grid_blocks", ct.c_int32), ("kahan", ct.c_int32),
+        ("far_max", ct.c_int32 * 3),
     ]
 
 
@@ -54,7 +55,7 @@ class VdwStats(ct.Structure):
     _fields_ = [
         ("retained", ct.c_int64), ("pairs", ct.c_double), ("pair_kernel_ms", ct.c_float),
         ("lds_rows", ct.c_int32), ("block_threads", ct.c_int32), ("j_chunks", ct.c_int32), ("grid_blocks", ct.c_int32),
-        ("diag_items", ct.c_int32),
+        ("diag_items", ct.c_int32), ("far_pairs", ct.c_double),
     ]
 
 

@@ -88,6 +88,7 @@ class Opts:
     j_chunks: int = 0
     grid_blocks: int = 0
     kahan: int = 0
+    far_max: tuple = (0, 0, 0)
 
     def c(self) -> L.VdwOpts:
         o = L.VdwOpts()
@@ -102,6 +103,8 @@ class Opts:
         o.j_chunks = self.j_chunks
         o.grid_blocks = self.grid_blocks
         o.kahan = self.kahan
+        for a in range(3):
+            o.far_max[a] = int(self.far_max[a])
         return o
 
 
@@ -370,7 +373,7 @@ def last_stats() -> dict:
     L.check(L.lib().vdw_last_stats(ct.byref(s)))
     return dict(retained=s.retained, pairs=s.pairs, pair_kernel_ms=s.pair_kernel_ms, lds_rows=s.lds_rows,
                 block_threads=s.block_threads, j_chunks=s.j_chunks, grid_blocks=s.grid_blocks,
-                diag_items=s.diag_items)
+                diag_items=s.diag_items, far_pairs=s.far_pairs)
 
 
 def set_timing(on: bool):

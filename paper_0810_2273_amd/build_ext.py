@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC_DIR = os.path.join(HERE, "csrc")
-SOURCES = ["util.hip", "table.hip", "q0.hip", "pair.hip", "xc.hip", "spectral.hip"]
+SOURCES = ["util.hip", "table.hip", "q0.hip", "pair.hip", "xc.hip", "spectral.hip", "far.hip"]
 LIB = os.path.join(HERE, "libvdwdf.so")
 ARCH = os.environ.get("VDW_OFFLOAD_ARCH", "gfx950")
 

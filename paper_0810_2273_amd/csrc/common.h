@@ -24,6 +24,37 @@ struct GridDev {
     int32_t spec[3];       // Fourier derivative on axis a (spectral gradient, periodic axis)
 };
 
+// Kept point as the pair kernels read it: grid coordinates (exact
+// integers), n, a = q h_x / (2 dD), b = sqrt(n_sigma - 1) a, w = x^2 + y^2
+// + z^2 (exact); FP32 records for VDW_FP32C, FP64 for VDW_FP64.
+struct alignas(32) RecF {
+    float x, y, z, n, a, b, w, pad;
+};
+struct alignas(64) RecD {
+    double x, y, z, n, a, b, w, pad;
+};
+
+// ---- far image shell (far.hip) ----
+// Shell of one density: lattice vectors m with |m_a| <= hi[a], except those
+// with every |m_a| <= lo[a] (hi = far_max, lo = image_max on periodic axes,
+// both 0 elsewhere).  T is tabulated at every grid displacement (d_x, d_y,
+// d_z), |d_a| < n_a, entry (d_x + n_x - 1) + (2 n_x - 1) ((d_y + n_y - 1) +
+// (2 n_y - 1) (d_z + n_z - 1)), as sum_shell 1 / m^3 with m = |d - L|^2 /
+// h_x^2 (the pair kernel's distance unit).
+struct FarGeo {
+    int32_t nx, ny, nz;
+    int32_t lo[3], hi[3];
+    double en[9];  // step vectors e_a / h_x (rows)
+};
+int64_t far_table_entries(const FarGeo &g);
+int launch_far_table(const FarGeo &g, double *T, hipStream_t s);
+// Far rows of the N kept points (records in compact order, N read on the
+// device from *nkept, at most nmax): far0[i] = sum_j n_j phi_far(i, j) and
+// (far_q non-null) far_q[i] = qscale sum_j n_j d phi_far(i, j) / d a_i, with
+// phi_far = -casym T_ij / (a_i^2 a_j^2 (a_i^2 + a_j^2)), j = i included.
+int launch_far_rows(const FarGeo &g, int fp64, const void *recs, const int64_t *nkept, int64_t nmax,
+                    const double *T, double casym, double qscale, double *far0, double *far_q, hipStream_t s);
+
 // ---- Fourier derivative along periodic axes (spectral.hip) ----
 // d_a per grid step of every line along `axis` of src (x fastest), written
 // to dst (same layout).

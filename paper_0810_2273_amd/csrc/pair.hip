@@ -84,15 +84,6 @@ struct Seg {
     int64_t N, p_off, item_off, blk_off, nIB, items;
 };
 
-// Kept point: grid coordinates (exact integers), n, a = q h_x / (2 dD),
-// b = sqrt(n_sigma - 1) a, w = x^2 + y^2 + z^2 (exact).
-struct alignas(32) RecF {
-    float x, y, z, n, a, b, w, pad;
-};
-struct alignas(64) RecD {
-    double x, y, z, n, a, b, w, pad;
-};
-
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -1073,6 +1064,8 @@ struct FinArgs {
     double *blockE;
     double *dEdn;   // direct part scattered to the grid (potential)
     double *dEdq;   // dE/dq scattered to the grid (potential)
+    const double *far;   // far-shell rows (compact order): S0 terms, then (potential) Sq terms; or NULL
+    int64_t far_stride;
 };
 
 // phi~(D, 0) and d phi~/dD from the FP64 table (asymptote at D >= D_max).
@@ -1169,6 +1162,10 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
                 if (F.img) S0L += (double)jp[iL * F.jstride + k];
                 if (F.adj) Sq += (double)jp[iq * F.jstride + k] * (sg.hx / (2.0 * F.dD));
             }
+        }
+        if (F.far) {
+            S0L += F.far[p];
+            if (F.adj) Sq += F.far[F.far_stride + p];
         }
         const int64_t g = F.gidx[p];
         const double nn = F.n[g], q = F.q0[g];
@@ -1347,7 +1344,8 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, dEdq, total;
+    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, dEdq, fartab, far,
+        total;
     int64_t nblocks, slots, rows, fin_blocks, Gtot;
 };
 
@@ -1362,6 +1360,8 @@ struct Plan {
     bool skew = false;  // some density has a skew cell: the general-metric kernels
     bool spec = false;  // the (single) density takes the Fourier derivative on some axis
     GridDev g0;         // the first density's grid
+    bool far = false;   // far image shell (single density)
+    FarGeo fg;          // its shell and geometry
     int JC = 8192;
     int tpb = kPairThreads;     // pair-kernel workgroup size
     int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
@@ -1552,6 +1552,36 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             }
     if (P->nimg > 4096) return fail(VDW_EINVAL, "too many images (%d)", P->nimg);
     P->img = P->nimg > 1 || o->r_cut > 0.0;
+    // far image shell: the lattice vectors up to far_max on periodic axes
+    // that are not near images
+    P->far = false;
+    {
+        const int per[3] = {P->segs[0].px, P->segs[0].py, P->segs[0].pz};
+        double vecs = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            if (o->far_max[a] < 0) return fail(VDW_EINVAL, "far_max must be >= 0");
+            if (per[a] && o->far_max[a] > 0) P->far = true;
+            if (per[a]) vecs *= 2.0 * o->far_max[a] + 1.0;
+        }
+        if (P->far) {
+            if (B > 1) return fail(VDW_EUNSUPPORTED, "the far image shell is not available to batched calls");
+            if (o->r_cut > 0.0) return fail(VDW_EINVAL, "the far image shell is defined without a distance cut");
+            for (int a = 0; a < 3; ++a)
+                if (per[a] && o->far_max[a] < m[a])
+                    return fail(VDW_EINVAL, "far_max[%d] = %d is below image_max[%d] = %d", a, o->far_max[a], a, m[a]);
+            if (vecs > 4194304.0) return fail(VDW_EINVAL, "far shell of %.0f lattice vectors (at most 2^22)", vecs);
+            FarGeo &f = P->fg;
+            const Seg &s0 = P->segs[0];
+            f.nx = s0.nx;
+            f.ny = s0.ny;
+            f.nz = s0.nz;
+            for (int a = 0; a < 3; ++a) {
+                f.lo[a] = per[a] ? m[a] : 0;
+                f.hi[a] = per[a] ? o->far_max[a] : 0;
+            }
+            for (int k = 0; k < 9; ++k) f.en[k] = s0.e[k] / s0.hx;
+        }
+    }
     P->NI = P->NJ = 1 + (P->img ? 1 : 0) + (adj ? 1 : 0);
 
     Layout &L = P->L;
@@ -1590,6 +1620,10 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     off = align256(off + (4 * B + 1) * sizeof(double));
     L.dEdq = off;
     if (adj) off = align256(off + Gtot * sizeof(double));
+    L.fartab = off;
+    if (P->far) off = align256(off + far_table_entries(P->fg) * sizeof(double));
+    L.far = off;
+    if (P->far) off = align256(off + 2 * Gtot * sizeof(double));
     L.total = off;
     return VDW_OK;
 }
@@ -1869,6 +1903,16 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     sa.fp64 = E.fp64;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)L.nblocks), dim3(kCompactThreads), 0, s, sa);
     VDW_HIP(hipGetLastError());
+    double *far = (double *)(w + L.far);
+    if (P.far) {
+        // far image shell (a single density): lattice sums, then its rows
+        double *T = (double *)(w + L.fartab);
+        int rc = launch_far_table(P.fg, T, s);
+        if (rc) return rc;
+        rc = launch_far_rows(P.fg, E.fp64, recs, hdr + HDR_NTOTAL, L.Gtot, T, E.pa.casym, P.segs[0].hx / E.pa.dD2,
+                             far, E.adj ? far + L.Gtot : nullptr, s);
+        if (rc) return rc;
+    }
 
     // pair kernel
     PairPtrs pp;
@@ -1919,6 +1963,8 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.dD = E.dD;
     fa.Dmax = E.Dmax;
     fa.casym = E.casym;
+    fa.far = P.far ? far : nullptr;
+    fa.far_stride = L.Gtot;
     fa.blockE = blockE;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
@@ -1976,6 +2022,7 @@ void set_stats(const Exec &E, const double *host, float ms)
     g_stats.j_chunks = E.P.JC / 1024;
     g_stats.grid_blocks = E.grid;
     g_stats.diag_items = E.P.ND;
+    g_stats.far_pairs = E.P.far ? (double)retained * (double)retained : 0.0;
 }
 
 // The whole pipeline for B densities, energies read back to the host.

@@ -228,3 +228,54 @@ def test_cubic_interpolant_host_validation(L):
     assert lib.enl_energy(ct.byref(g), dummy, dummy, dummy, dummy, ct.byref(tp), ct.byref(o), dummy, 1 << 30, E,
                           None) == L.VDW_EUNSUPPORTED
     assert b"FP64" in lib.vdw_last_error()
+
+
+def test_far_shell_host_validation(L):
+    """far_max: >= 0, no distance cut, >= image_max on periodic axes, a
+    bounded shell, one density per call; the workspace grows by the table
+    of T over the grid displacements and two row arrays.  Sizes only: no
+    call here reaches the device."""
+    lib = L.lib()
+    lib.enl_workspace_size.restype = ct.c_size_t
+    lib.enl_batched_workspace_size.restype = ct.c_size_t
+    g = L.VdwGrid()
+    for a, (n, per) in enumerate(((8, 1), (6, 1), (10, 0))):
+        g.n[a] = n
+        g.cell[a][a] = 0.5 * n
+        g.periodic[a] = per
+    tp = L.VdwTableParams(64, 16, 12.0, 8, 12, 4.0, 64.0)
+
+    def opts(**kw):
+        o = L.VdwOpts()
+        o.n_cut = 1e-5
+        o.self_term = 1
+        o.table_lds_rows = -1
+        for k, v in kw.items():
+            if k in ("image_max", "far_max"):
+                for a in range(3):
+                    getattr(o, k)[a] = v[a]
+            else:
+                setattr(o, k, v)
+        return o
+
+    def size(o, B=1):
+        arr = (L.VdwGrid * B)(*([g] * B))
+        return lib.enl_batched_workspace_size(B, arr, ct.byref(tp), ct.byref(o))
+
+    base = size(opts(image_max=(1, 1, 0)))
+    far = size(opts(image_max=(1, 1, 0), far_max=(4, 3, 0)))
+    assert base > 0 and far > 0
+    ne = (2 * 8 - 1) * (2 * 6 - 1) * (2 * 10 - 1)
+    assert far - base >= 8 * ne + 2 * 8 * (8 * 6 * 10)
+    # far_max on a non-periodic axis alone selects nothing
+    assert size(opts(image_max=(1, 1, 0), far_max=(0, 0, 7))) == base
+    assert size(opts(far_max=(-1, 0, 0))) == 0
+    assert b"far_max" in lib.vdw_last_error()
+    assert size(opts(image_max=(2, 1, 0), far_max=(1, 3, 0))) == 0
+    assert b"below image_max" in lib.vdw_last_error()
+    assert size(opts(r_cut=10.0, far_max=(3, 3, 0))) == 0
+    assert b"distance cut" in lib.vdw_last_error()
+    assert size(opts(far_max=(3000, 3000, 0))) == 0
+    assert b"lattice vectors" in lib.vdw_last_error()
+    assert size(opts(far_max=(3, 3, 0)), B=2) == 0
+    assert b"batched" in lib.vdw_last_error()
