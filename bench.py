@@ -44,6 +44,14 @@ PROFILE_COUNTERS = {
     "kr": {"source": "profiles/pair_kernel_kr_scan96_fp32c.md", "executed_tflops": 47.5, "executed_frac": 0.302,
            "valu_instructions_per_issue_slot": 1.11, "lane_instructions_per_unordered_pair": 39.9},
 }
+# Far image shell (FP64): algorithmic FLOP per ordered pair of the row pass
+# (a_i^2 a_j^2 (a_i^2 + a_j^2), its reciprocal, the weighted sum and the
+# q-derivative term) and per (displacement, lattice vector) term of the
+# lattice-sum table (the displacement mapped by the step matrix, |.|^2, the
+# cube, its reciprocal, the sum); peak: MI355X FP64 vector.
+FLOP_PER_FAR_PAIR = 12
+FLOP_PER_FAR_TERM = 30
+PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
@@ -56,9 +64,11 @@ def parse():
     p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--R", type=float, default=7.0, help="separation of the kr1 workload (bohr)")
-    p.add_argument("--workload", default="kr", choices=["kr", "kr1", "slab", "hexslab", "batch", "dimer24"],
-                   help="kr: the Kr2-like dimer scan (the reported metric); kr1: one dimer at --R; slab, batch, "
-                        "dimer24: the other cases")
+    p.add_argument("--far", type=int, default=32, help="far image shell of the slabfar workload: |m|,|p| <= far")
+    p.add_argument("--workload", default="kr",
+                   choices=["kr", "kr1", "slab", "hexslab", "slabfar", "batch", "dimer24"],
+                   help="kr: the Kr2-like dimer scan (the reported metric); kr1: one dimer at --R; slab, hexslab, "
+                        "slabfar (near images plus the far shell), batch, dimer24: the other cases")
     p.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison run")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-rows", type=int, default=0, help="oracle rows in the CPU sample (0: auto)")
@@ -100,6 +110,12 @@ def workloads(a, W):
         desc = ("Xe-like slab on the hexagonal cell of a close-packed monolayer (a = (8.6, 0, 0), b = (4.3, 7.45, 0), "
                 "c = (0, 0, 40) bohr), 48x48x224 grid, periodic in a and b, images |m|,|p|<=4, r<=30 bohr, n_cut=1e-5, "
                 "table 2048x64, energy + potential fused")
+    elif a.workload == "slabfar":
+        wls = [W.xe_slab()]
+        wls[0].image_max, wls[0].r_cut = (2, 2, 0), 0.0
+        desc = ("Xe-like slab, 48x48x224 grid of an 8.6x8.6x40 bohr cell, periodic x,y, no distance cut: images "
+                "|m|,|p|<=2 with the table, the far shell |m|,|p|<=%d with the large-D asymptote (one lattice-sum "
+                "pass), n_cut=1e-5, table 2048x64, energy + potential fused" % a.far)
     elif a.workload == "batch":
         wls = W.molecule_batch(64)
         desc = ("64 molecule densities, 16^3..64^3 grids h=0.3 bohr, n_cut=1e-5, table 2048x64, one batched "
@@ -170,9 +186,10 @@ def main():
     batched = len(wls) > 1
 
     def opts(prec):
+        far = (a.far, a.far, 0) if a.workload == "slabfar" else (0, 0, 0)
         return V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec, kahan=a.kahan,
                       table_lds_rows=a.lds_rows, j_chunks=a.j_chunks, grid_blocks=a.grid_blocks,
-                      block_threads=a.block_threads)
+                      block_threads=a.block_threads, far_max=far)
 
     graph = batched and not a.no_graph
     plans = {}
@@ -247,7 +264,9 @@ def main():
         a.j_chunks, a.block_threads = tuned.j_chunks, tuned.block_threads
         print(f"# autotune: block_threads={a.block_threads} j_chunks={a.j_chunks}", file=sys.stderr, flush=True)
     dt, E32, v32, kms32, st = timed(main_prec, a.steps, a.warmup)
-    pairs = st["pairs"]
+    near_pairs = st["pairs"]
+    far_pairs = st["far_pairs"]
+    pairs = near_pairs + far_pairs  # the far shell's pairs count once each (their lattice sums folded in)
     value = pairs * a.steps / dt
     out = {
         "metric": "pair-evals/s E_nl+v_nl, FP32-compensated vs FP64 on GPU at |dE|/|E|<=1e-6",
@@ -276,7 +295,7 @@ def main():
         },
     }
     fpp = FLOP_PER_UNORDERED_PAIR_ENERGY if a.workload == "dimer24" else FLOP_PER_UNORDERED_PAIR
-    achieved = 0.5 * pairs * fpp / (kms32 * 1e-3) / 1e12
+    achieved = 0.5 * near_pairs * fpp / (kms32 * 1e-3) / 1e12
     out["roofline"] = {
         "bound": "alu",
         "achieved": achieved,
@@ -286,7 +305,7 @@ def main():
         "traffic": TRAFFIC_BYTES.get(a.workload) if a.workload != "kr1" or a.R == 7.0 else None,
         "kernel": "pair_kernel<%s, %s, %s>" % ("double" if a.workload == "dimer24" else "float",
                                                 "energy" if a.workload == "dimer24" else "ADJ",
-                                                "IMG" if a.workload in ("slab", "hexslab") else "noIMG"),
+                                                "IMG" if a.workload in ("slab", "hexslab", "slabfar") else "noIMG"),
         "kernel_ms": kms32,
         "flop_per_unordered_pair": fpp,
     }
@@ -301,6 +320,21 @@ def main():
             scan.append({"R_bohr": R, "E_nl": e_ab, "E_nl_minus_E_inf": e_ab - e_a - e_b})
         out["scan"] = scan
     out["table_build_s"] = t_table
+    if far_pairs:
+        nvec = (2 * a.far + 1) ** 2 - (2 * wl.image_max[0] + 1) * (2 * wl.image_max[1] + 1)
+        entries = (2 * wl.n[0] - 1) * (2 * wl.n[1] - 1) * (2 * wl.n[2] - 1)
+        flop = far_pairs * FLOP_PER_FAR_PAIR + entries * nvec * FLOP_PER_FAR_TERM
+        fms = st["far_kernel_ms"]
+        out["far_shell"] = {
+            "near_image_max": list(wl.image_max), "far_max": [a.far, a.far, 0], "lattice_vectors": nvec,
+            "table_entries": entries, "far_pairs": far_pairs, "image_pairs_covered": far_pairs * nvec,
+            "far_kernels_ms": fms, "near_pair_kernel_ms": kms32,
+            "roofline": {"bound": "alu", "achieved": flop / (fms * 1e-3) / 1e12 if fms > 0 else None,
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": flop / (fms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS if fms > 0 else None,
+                         "kernels": "far_table_kernel + far_rows_kernel", "flop_per_pair": FLOP_PER_FAR_PAIR,
+                         "flop_per_table_term": FLOP_PER_FAR_TERM},
+        }
     if not a.no_fp64 and a.workload != "dimer24":
         steps64 = max(1, a.steps // 2)
         dt64, E64, v64, kms64, _ = timed(V.VDW_FP64, steps64, 1)

@@ -55,7 +55,7 @@ class VdwStats(ct.Structure):
     _fields_ = [
         ("retained", ct.c_int64), ("pairs", ct.c_double), ("pair_kernel_ms", ct.c_float),
         ("lds_rows", ct.c_int32), ("block_threads", ct.c_int32), ("j_chunks", ct.c_int32), ("grid_blocks", ct.c_int32),
-        ("diag_items", ct.c_int32), ("far_pairs", ct.c_double),
+        ("diag_items", ct.c_int32), ("far_pairs", ct.c_double), ("far_kernel_ms", ct.c_float),
     ]
 
 

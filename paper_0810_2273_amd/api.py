@@ -373,7 +373,7 @@ def last_stats() -> dict:
     L.check(L.lib().vdw_last_stats(ct.byref(s)))
     return dict(retained=s.retained, pairs=s.pairs, pair_kernel_ms=s.pair_kernel_ms, lds_rows=s.lds_rows,
                 block_threads=s.block_threads, j_chunks=s.j_chunks, grid_blocks=s.grid_blocks,
-                diag_items=s.diag_items, far_pairs=s.far_pairs)
+                diag_items=s.diag_items, far_pairs=s.far_pairs, far_kernel_ms=s.far_kernel_ms)
 
 
 def set_timing(on: bool):

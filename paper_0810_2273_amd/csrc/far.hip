@@ -8,11 +8,12 @@
 //
 //   far_table  one thread per displacement: the shell's lattice sum in
 //              FP64, in a fixed order
-//   far_rows   one lane per kept point i (two per thread), every j of the
-//              density streamed through scalar loads; T gathered at the
-//              displacement (the lanes of a wavefront are one brick of
-//              points, so their gathers hit a few cache lines); FP64
-//              sums, the pair i = j included
+//   far_rows   one lane per kept point i (two per thread), the j-points of
+//              one chunk of the density streamed through scalar loads; T
+//              gathered at the displacement (the lanes of a wavefront are
+//              one brick of points, so their gathers hit a few cache
+//              lines); FP64 sums per chunk, the pair i = j included; the
+//              chunk partials are added in a fixed order later
 #include <math.h>
 
 #include "common.h"
@@ -22,7 +23,7 @@ namespace vdw {
 namespace {
 
 constexpr int kFarThreads = 256;
-constexpr int kFarIPL = 2;  // kept points per thread (amortises the wave-uniform j work)
+constexpr int kFarIPL = 2;  // kept points per thread (four: 106 VGPRs, measured no faster)
 
 __global__ __launch_bounds__(kFarThreads) void far_table_kernel(FarGeo g, int64_t ne, double *__restrict__ T)
 {
@@ -50,53 +51,95 @@ __global__ __launch_bounds__(kFarThreads) void far_table_kernel(FarGeo g, int64_
     T[e] = s;
 }
 
-template <typename Rec>
+// 1 / x for x > 0 in the normal range: the hardware estimate refined by two
+// Newton steps (each squares the relative error), to about one ulp.
+__device__ inline double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Rows of block x, j chunk y (of gridDim.y): partial sums of the chunk's
+// j-points, written to part[y][i] (energy) and (ADJ) part[C + y][i]
+// (dE/da_i).  The j loop takes groups of kFarJ points so that their table
+// gathers are in flight together.
+constexpr int kFarJ = 4;
+
+template <typename Rec, bool ADJ>
 __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const Rec *__restrict__ recs,
                                                                const int64_t *__restrict__ nkept,
                                                                const double *__restrict__ T, double casym,
-                                                               double qscale, double *__restrict__ far0,
-                                                               double *__restrict__ far_q)
+                                                               double qscale, int64_t stride,
+                                                               double *__restrict__ part)
 {
     const int64_t N = *nkept;
     const int64_t i0 = (int64_t)blockIdx.x * (kFarThreads * kFarIPL);
     if (i0 >= N) return;  // N >= 1 below
-    const int64_t ex = 2 * g.nx - 1, ey = 2 * g.ny - 1;
-    int64_t base[kFarIPL];
+    const int C = gridDim.y, c = blockIdx.y;
+    const int64_t len = (N + C - 1) / C;
+    const int64_t j0 = min(N, (int64_t)c * len), j1 = min(N, j0 + len);
+    // table offsets fit 32 bits (the host bounds the table)
+    const int ex = 2 * g.nx - 1, ey = 2 * g.ny - 1;
+    int base[kFarIPL];
     double pi[kFarIPL], g2[kFarIPL], a2[kFarIPL], acc[kFarIPL], accq[kFarIPL];
 #pragma unroll
     for (int p = 0; p < kFarIPL; ++p) {
         const int64_t i = i0 + threadIdx.x + (int64_t)kFarThreads * p;
         const Rec R = recs[i < N ? i : N - 1];
         // table entry of displacement r_i - r_j is base - offset(j)
-        base[p] = ((int64_t)R.x + g.nx - 1) + ex * (((int64_t)R.y + g.ny - 1) + ey * ((int64_t)R.z + g.nz - 1));
+        base[p] = ((int)R.x + g.nx - 1) + ex * (((int)R.y + g.ny - 1) + ey * ((int)R.z + g.nz - 1));
         const double a = (double)R.a;
         pi[p] = a * a;
         g2[p] = 2.0 / a;
         a2[p] = 2.0 * a;
         acc[p] = accq[p] = 0.0;
     }
-    const bool adj = far_q != nullptr;
-    for (int64_t j = 0; j < N; ++j) {
-        const Rec J = recs[j];
-        const int64_t oj = (int64_t)J.x + ex * ((int64_t)J.y + ey * (int64_t)J.z);
-        const double aj = (double)J.a, pj = aj * aj, nj = (double)J.n;
+    // one pair: w = n_j T / (p_i p_j (p_i + p_j)); d/da_i of -1 / (a_i^2 a_j^2 pp)
+    // is (2 / a_i + 2 a_i / pp) / (a_i^2 a_j^2 pp)
+    auto term = [&](int p, double t, double pj, double nj) {
+        const double X = pi[p] * pj, pp = pi[p] + pj;
+        const double Rinv = rcp64(X * pp);
+        const double w = nj * t * Rinv;
+        acc[p] += w;
+        if (ADJ) accq[p] += w * (g2[p] + a2[p] * (Rinv * X));
+    };
+    int64_t j = j0;
+    for (; j + kFarJ <= j1; j += kFarJ) {
+        int oj[kFarJ];
+        double pj[kFarJ], nj[kFarJ], t[kFarJ][kFarIPL];
 #pragma unroll
-        for (int p = 0; p < kFarIPL; ++p) {
-            const double t = T[base[p] - oj];
-            const double X = pi[p] * pj, pp = pi[p] + pj;
-            const double Rinv = 1.0 / (X * pp);
-            const double w = nj * t * Rinv;
-            acc[p] += w;
-            // d/da_i of -1 / (a_i^2 a_j^2 pp) is (2 / a_i + 2 a_i / pp) / (a_i^2 a_j^2 pp)
-            if (adj) accq[p] += w * (g2[p] + a2[p] * (Rinv * X));
+        for (int u = 0; u < kFarJ; ++u) {
+            const Rec J = recs[j + u];
+            oj[u] = (int)J.x + ex * ((int)J.y + ey * (int)J.z);
+            const double aj = (double)J.a;
+            pj[u] = aj * aj;
+            nj[u] = (double)J.n;
         }
+#pragma unroll
+        for (int u = 0; u < kFarJ; ++u)
+#pragma unroll
+            for (int p = 0; p < kFarIPL; ++p) t[u][p] = T[(unsigned)(base[p] - oj[u])];
+#pragma unroll
+        for (int u = 0; u < kFarJ; ++u)
+#pragma unroll
+            for (int p = 0; p < kFarIPL; ++p) term(p, t[u][p], pj[u], nj[u]);
+    }
+    for (; j < j1; ++j) {
+        const Rec J = recs[j];
+        const int oj = (int)J.x + ex * ((int)J.y + ey * (int)J.z);
+        const double aj = (double)J.a;
+#pragma unroll
+        for (int p = 0; p < kFarIPL; ++p) term(p, T[(unsigned)(base[p] - oj)], aj * aj, (double)J.n);
     }
 #pragma unroll
     for (int p = 0; p < kFarIPL; ++p) {
         const int64_t i = i0 + threadIdx.x + (int64_t)kFarThreads * p;
         if (i >= N) continue;
-        far0[i] = -casym * acc[p];
-        if (adj) far_q[i] = casym * qscale * accq[p];
+        part[(int64_t)c * stride + i] = -casym * acc[p];
+        if (ADJ) part[(int64_t)(C + c) * stride + i] = casym * qscale * accq[p];
     }
 }
 
@@ -116,17 +159,37 @@ int launch_far_table(const FarGeo &g, double *T, hipStream_t s)
     return VDW_OK;
 }
 
+int far_chunks(int64_t nmax)
+{
+    // enough blocks for about 16 wavefronts per SIMD when every point is
+    // kept, chunks of at least 1024 points
+    const int64_t rb = (nmax + kFarThreads * kFarIPL - 1) / (kFarThreads * kFarIPL);
+    int64_t C = rb > 0 ? (4096 + rb - 1) / rb : 1;
+    if (C > nmax / 1024) C = nmax / 1024;
+    if (C > kFarMaxChunks) C = kFarMaxChunks;
+    return C < 1 ? 1 : (int)C;
+}
+
 int launch_far_rows(const FarGeo &g, int fp64, const void *recs, const int64_t *nkept, int64_t nmax,
-                    const double *T, double casym, double qscale, double *far0, double *far_q, hipStream_t s)
+                    const double *T, double casym, double qscale, int chunks, int adj, double *part, hipStream_t s)
 {
     if (nmax < 1) return VDW_OK;
-    const unsigned blocks = (unsigned)((nmax + kFarThreads * kFarIPL - 1) / (kFarThreads * kFarIPL));
-    if (fp64)
-        hipLaunchKernelGGL(far_rows_kernel<RecD>, dim3(blocks), dim3(kFarThreads), 0, s, g, (const RecD *)recs, nkept,
-                           T, casym, qscale, far0, far_q);
+    if (chunks < 1 || chunks > kFarMaxChunks) return fail(VDW_EINVAL, "internal: %d far chunks", chunks);
+    const dim3 grid((unsigned)((nmax + kFarThreads * kFarIPL - 1) / (kFarThreads * kFarIPL)), (unsigned)chunks);
+    const RecD *rd = (const RecD *)recs;
+    const RecF *rf = (const RecF *)recs;
+    if (fp64 && adj)
+        hipLaunchKernelGGL((far_rows_kernel<RecD, true>), grid, dim3(kFarThreads), 0, s, g, rd, nkept, T, casym, qscale,
+                           nmax, part);
+    else if (fp64)
+        hipLaunchKernelGGL((far_rows_kernel<RecD, false>), grid, dim3(kFarThreads), 0, s, g, rd, nkept, T, casym,
+                           qscale, nmax, part);
+    else if (adj)
+        hipLaunchKernelGGL((far_rows_kernel<RecF, true>), grid, dim3(kFarThreads), 0, s, g, rf, nkept, T, casym,
+                           qscale, nmax, part);
     else
-        hipLaunchKernelGGL(far_rows_kernel<RecF>, dim3(blocks), dim3(kFarThreads), 0, s, g, (const RecF *)recs, nkept,
-                           T, casym, qscale, far0, far_q);
+        hipLaunchKernelGGL((far_rows_kernel<RecF, false>), grid, dim3(kFarThreads), 0, s, g, rf, nkept, T, casym,
+                           qscale, nmax, part);
     VDW_HIP(hipGetLastError());
     return VDW_OK;
 }

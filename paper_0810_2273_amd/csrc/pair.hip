@@ -967,7 +967,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 R jSc = 0, jSL = 0, jSq = 0;
                 for (int L = 0; L < nimg; ++L) {
                     R lx = 0, ly = 0, lz = 0;
-                    bool home = true, masked = IMG;
+                    bool home = true, masked = prune;  // no cut: every tile unmasked
                     if (IMG) {
                         lx = (R)(imgs[4 * L + 0] * sg.nx);
                         ly = (R)(imgs[4 * L + 1] * sg.ny);
@@ -1064,8 +1064,10 @@ struct FinArgs {
     double *blockE;
     double *dEdn;   // direct part scattered to the grid (potential)
     double *dEdq;   // dE/dq scattered to the grid (potential)
-    const double *far;   // far-shell rows (compact order): S0 terms, then (potential) Sq terms; or NULL
+    const double *far;   // far-shell row partials (compact order): far_chunks S0 arrays, then (potential)
+                         // far_chunks Sq arrays, far_stride apart; or NULL
     int64_t far_stride;
+    int far_chunks;
 };
 
 // phi~(D, 0) and d phi~/dD from the FP64 table (asymptote at D >= D_max).
@@ -1164,8 +1166,10 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
             }
         }
         if (F.far) {
-            S0L += F.far[p];
-            if (F.adj) Sq += F.far[F.far_stride + p];
+            for (int c = 0; c < F.far_chunks; ++c) {
+                S0L += F.far[c * F.far_stride + p];
+                if (F.adj) Sq += F.far[(F.far_chunks + c) * F.far_stride + p];
+            }
         }
         const int64_t g = F.gidx[p];
         const double nn = F.n[g], q = F.q0[g];
@@ -1362,6 +1366,7 @@ struct Plan {
     GridDev g0;         // the first density's grid
     bool far = false;   // far image shell (single density)
     FarGeo fg;          // its shell and geometry
+    int far_chunks = 1; // j chunks of its row pass (partial sums per chunk)
     int JC = 8192;
     int tpb = kPairThreads;     // pair-kernel workgroup size
     int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
@@ -1580,6 +1585,9 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
                 f.hi[a] = per[a] ? o->far_max[a] : 0;
             }
             for (int k = 0; k < 9; ++k) f.en[k] = s0.e[k] / s0.hx;
+            if (far_table_entries(f) >= ((int64_t)1 << 31))
+                return fail(VDW_EINVAL, "grid too large for the far-shell table (2^31 displacements)");
+            P->far_chunks = far_chunks(Gtot);
         }
     }
     P->NI = P->NJ = 1 + (P->img ? 1 : 0) + (adj ? 1 : 0);
@@ -1623,7 +1631,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     L.fartab = off;
     if (P->far) off = align256(off + far_table_entries(P->fg) * sizeof(double));
     L.far = off;
-    if (P->far) off = align256(off + 2 * Gtot * sizeof(double));
+    if (P->far) off = align256(off + 2 * (size_t)P->far_chunks * Gtot * sizeof(double));
     L.total = off;
     return VDW_OK;
 }
@@ -1853,7 +1861,7 @@ int upload(const Exec &E, hipStream_t s)
 // 4B+1 doubles: 3B energies, B retained counts, the non-finite flag.
 int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *grad_d, const double *dqdn_d,
             const double *dqdg_d, const double *phi_d, const float *phi_f, double *dEdn_d, double *res, hipStream_t s,
-            hipEvent_t ev0, hipEvent_t ev1)
+            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t evf0 = nullptr, hipEvent_t evf1 = nullptr)
 {
     const Plan &P = E.P;
     const Layout &L = P.L;
@@ -1907,11 +1915,13 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     if (P.far) {
         // far image shell (a single density): lattice sums, then its rows
         double *T = (double *)(w + L.fartab);
+        if (evf0) VDW_HIP(hipEventRecord(evf0, s));
         int rc = launch_far_table(P.fg, T, s);
         if (rc) return rc;
         rc = launch_far_rows(P.fg, E.fp64, recs, hdr + HDR_NTOTAL, L.Gtot, T, E.pa.casym, P.segs[0].hx / E.pa.dD2,
-                             far, E.adj ? far + L.Gtot : nullptr, s);
+                             P.far_chunks, E.adj, far, s);
         if (rc) return rc;
+        if (evf1) VDW_HIP(hipEventRecord(evf1, s));
     }
 
     // pair kernel
@@ -1965,6 +1975,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.casym = E.casym;
     fa.far = P.far ? far : nullptr;
     fa.far_stride = L.Gtot;
+    fa.far_chunks = P.far_chunks;
     fa.blockE = blockE;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
@@ -2005,7 +2016,7 @@ bool any_spectral(int B, const vdw_grid *grids)
 thread_local vdw_stats g_stats;
 thread_local int g_timing = 0;
 
-void set_stats(const Exec &E, const double *host, float ms)
+void set_stats(const Exec &E, const double *host, float ms, float far_ms)
 {
     double pairs = 0.0;
     int64_t retained = 0;
@@ -2023,6 +2034,7 @@ void set_stats(const Exec &E, const double *host, float ms)
     g_stats.grid_blocks = E.grid;
     g_stats.diag_items = E.P.ND;
     g_stats.far_pairs = E.P.far ? (double)retained * (double)retained : 0.0;
+    g_stats.far_kernel_ms = far_ms;
 }
 
 // The whole pipeline for B densities, energies read back to the host.
@@ -2040,29 +2052,38 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     if (rc) return rc;
     rc = upload(E, s);
     if (rc) return rc;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evf0 = nullptr, evf1 = nullptr;
     if (g_timing) {
         VDW_HIP(hipEventCreate(&ev0));
         VDW_HIP(hipEventCreate(&ev1));
+        if (E.P.far) {
+            VDW_HIP(hipEventCreate(&evf0));
+            VDW_HIP(hipEventCreate(&evf1));
+        }
     }
     double *res = (double *)(E.ws + E.P.L.res);
-    rc = enqueue(E, n_d, q0_d, grad_d, dqdn_d, dqdg_d, phi_d, phi_f, dEdn_d, res, s, ev0, ev1);
+    rc = enqueue(E, n_d, q0_d, grad_d, dqdn_d, dqdg_d, phi_d, phi_f, dEdn_d, res, s, ev0, ev1, evf0, evf1);
     std::vector<double> host(4 * B + 1);
     if (!rc) {
         hipError_t e = hipMemcpyAsync(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = fail(VDW_EHIP, "reading the energies back: %s", hipGetErrorString(e));
     }
-    float ms = 0.0f;
+    float ms = 0.0f, far_ms = 0.0f;
     if (ev0) {
         if (!rc && hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess) ms = 0.0f;
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }
+    if (evf0) {
+        if (!rc && hipEventElapsedTime(&far_ms, evf0, evf1) != hipSuccess) far_ms = 0.0f;
+        (void)hipEventDestroy(evf0);
+        (void)hipEventDestroy(evf1);
+    }
     if (rc) return rc;
     if (host[4 * B] != 0.0) return fail(VDW_ENONFINITE, "the density holds NaN or Inf values");
     for (int k = 0; k < 3 * B; ++k) E_out[k] = host[k];
-    set_stats(E, host.data(), ms);
+    set_stats(E, host.data(), ms, far_ms);
     return VDW_OK;
 }
 

@@ -157,3 +157,32 @@ def test_far_shell_slab_full_size_sampled_potential(V, oracle, tables, prec, vto
     say(f"  sampled |dv|/|v| over {len(ks)} points = {rel:.3e}")
     assert rel <= vtol
     assert E[1] < 0
+
+
+def test_far_shell_approximation_on_the_slab(V):
+    """Xe slab at full size, energies only (FP32C): the shell's asymptote in
+    place of the table for rings 3-4 moves E_pairL by less than 1e-5 of
+    itself, under 1 % of what those rings contribute; the paper's setting
+    (three rings, r <= 30 bohr) and the shell out to 32 rings are printed."""
+    import torch
+
+    wl = W.xe_slab()
+    dev = torch.device("cuda:0")
+    table = V.build_phi_table(V.TableParams(n_D=2048, n_sigma=64, D_max=48.0), device=dev)
+    g = V.Grid(wl.n, wl.h, wl.periodic)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device=dev)
+    q0 = V.compute_q0(g, n, wl.n_cut)["q0"]
+
+    def e(near, far=(0, 0, 0), r_cut=0.0):
+        E = V.enl_energy(g, n, q0, table, V.Opts(n_cut=wl.n_cut, image_max=near, far_max=far, r_cut=r_cut))
+        say(f"  near {near} far {far} r_cut {r_cut}: E_pairL = {E[1]:.10e}  E = {sum(E):.10e}")
+        return E
+
+    exact4 = e((4, 4, 0))
+    near2 = e((2, 2, 0))
+    far4 = e((2, 2, 0), (4, 4, 0))
+    e((2, 2, 0), (32, 32, 0))
+    e((3, 3, 0), r_cut=30.0)
+    assert abs(far4[1] - exact4[1]) <= 1e-5 * abs(exact4[1])
+    assert abs(far4[1] - exact4[1]) <= 1e-2 * abs(near2[1] - exact4[1])
+    assert far4[0] == exact4[0] and far4[2] == exact4[2]
