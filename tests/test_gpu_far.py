@@ -186,3 +186,39 @@ def test_far_shell_approximation_on_the_slab(V):
     assert abs(far4[1] - exact4[1]) <= 1e-5 * abs(exact4[1])
     assert abs(far4[1] - exact4[1]) <= 1e-2 * abs(near2[1] - exact4[1])
     assert far4[0] == exact4[0] and far4[2] == exact4[2]
+
+
+def test_far_shell_in_a_graph_plan(V, oracle, tables):
+    """A one-density plan with the far shell, recorded as a HIP graph: three
+    replays (eager calls in between) equal each other bit for bit and equal
+    the oracle; a batch of two densities with a shell is refused."""
+    import torch
+
+    name, make, near, far = CASES[0]
+    wl = make()
+    tp, tab = tables[16]
+    g, og = _grids(V, oracle, wl)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    table = _gpu_table(V, tp, tab)
+    opts = V.Opts(n_cut=wl.n_cut, image_max=near, far_max=far, precision=0)
+    ref = oracle.evaluate(og, wl.rho, tab, tp, wl.n_cut, near, potential=True, far_max=far)
+    plan = V.BatchPlan([g], [0, wl.G], table, opts)
+    plan.capture(n)
+    first = None
+    for r in range(3):
+        plan.replay()
+        torch.cuda.synchronize()
+        E_r, v_r = plan.energies()[0], plan.dEdn.clone()
+        qd = V.compute_q0(g, n, wl.n_cut)
+        E_e, v_e = V.enl_potential(g, n, qd, table, opts)
+        torch.cuda.synchronize()
+        assert sum(E_r) == pytest.approx(ref.E, rel=1e-12)
+        assert sum(E_r) == pytest.approx(sum(E_e), rel=1e-14)
+        assert np.linalg.norm(v_r.cpu().numpy() - ref.dEdn) <= 1e-10 * np.linalg.norm(ref.dEdn)
+        if first is None:
+            first = (E_r, v_r)
+        else:
+            assert E_r == first[0] and torch.equal(v_r, first[1])
+    plan.close()
+    with pytest.raises(Exception):
+        V.BatchPlan([g, g], [0, wl.G, 2 * wl.G], table, opts)
