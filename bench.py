@@ -15,7 +15,10 @@ roofline of the pair kernel and the CPU oracle's rate on a sample.
 Roofline: the pair kernel is bound by vector ALU work.  It evaluates each
 unordered pair once for both orders; the algorithmic work of one such
 evaluation (energy + adjoint sums, table branch) is FLOP_PER_UNORDERED_PAIR
-FP32 operations (FMA counted as 2, transcendental as 1), so
+FP32 operations (FMA counted as 2, transcendental as 1: displacement 3,
+squared distance 5, square root 1, a_i + a_j 1, t_D 1, reciprocal 1, u 2,
+t_sigma 1, fractions 2, bilinear value 9, sigma slope 3, the two derivative
+products 4, the two q-derivatives 4, four accumulations 8), so
 achieved = (ordered pairs / 2) x FLOP_PER_UNORDERED_PAIR / (mean pair-kernel
 time from HIP events on the launch stream), against the 157.3 TFLOP/s FP32
 vector peak of MI355X.
