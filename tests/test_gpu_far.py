@@ -222,3 +222,39 @@ def test_far_shell_in_a_graph_plan(V, oracle, tables):
     plan.close()
     with pytest.raises(Exception):
         V.BatchPlan([g, g], [0, wl.G, 2 * wl.G], table, opts)
+
+
+def test_far_shell_edge_cases(V, oracle, tables):
+    """Nothing kept: all zero.  One kept point: its only pair terms are its
+    own far images, -C T(0) / (2 q^6) per unit n^2.  Two runs agree bit for
+    bit."""
+    import torch
+
+    tp, tab = tables[16]
+    table = _gpu_table(V, tp, tab)
+    wl = W.random_small(n=(9, 8, 7), h=(0.4, 0.45, 0.5), periodic=(1, 1, 0), seed=85, n_cut=2.2e-3)
+    g, og = _grids(V, oracle, wl)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+
+    def run(n_cut, prec=0):
+        qd = V.compute_q0(g, n, n_cut)
+        E, v = V.enl_potential(g, n, qd, table, V.Opts(n_cut=n_cut, image_max=(1, 1, 0), far_max=(5, 5, 0),
+                                                       precision=prec))
+        return E, v.cpu().numpy()
+
+    say("far edge: empty retained set")
+    E, v = run(1e6)
+    assert E == (0.0, 0.0, 0.0) and np.all(v == 0) and V.last_stats()["far_pairs"] == 0.0
+    say("far edge: one retained point")
+    top = float(wl.rho.max())
+    E, v = run(top)
+    ref = oracle.evaluate(og, wl.rho, tab, tp, top, (1, 1, 0), potential=True, far_max=(5, 5, 0))
+    assert V.last_stats()["retained"] == 1
+    assert E[0] == 0.0
+    assert E[1] == pytest.approx(ref.E_pairL, rel=1e-13) and E[1] < 0
+    assert np.linalg.norm(v - ref.dEdn) <= 1e-12 * np.linalg.norm(ref.dEdn)
+    say("far edge: determinism")
+    for prec in (0, 1):
+        a, va = run(wl.n_cut, prec)
+        b, vb = run(wl.n_cut, prec)
+        assert a == b and np.array_equal(va, vb)
