@@ -366,9 +366,10 @@ int enl_batch_plan_destroy(vdw_batch_plan *plan);
 /* ---------------------------------------------------------------------
  * Diagnostics of the last enl_* call on this host thread (after it
  * returned VDW_OK): retained points, logical pairs (ordered (i, j, L),
- * self pair excluded, before the distance cut), and kernel time of the
- * pair kernel in milliseconds measured with HIP events on `stream`
- * (0 unless timing was enabled with vdw_set_timing(1)).
+ * self pair excluded, before the distance cut), and kernel times of the
+ * pair kernel and of the far-shell kernels in milliseconds measured with
+ * HIP events on `stream` (0 unless timing was enabled with
+ * vdw_set_timing(1)).
  * ------------------------------------------------------------------- */
 typedef struct {
     int64_t retained;
@@ -380,6 +381,7 @@ typedef struct {
     int32_t grid_blocks;
     int32_t diag_items;     /* diagonal work items per row block */
     double  far_pairs;      /* ordered pairs (i, j) of the far-shell pass (N^2), or 0 */
+    float   far_kernel_ms;  /* far-shell table and row kernels (timing on), or 0 */
 } vdw_stats;
 
 int vdw_last_stats(vdw_stats *out);
