@@ -68,8 +68,8 @@ enum { VDW_FP64 = 0, VDW_FP32C = 1 };
  * second-order differences everywhere) or VDW_GRAD_SPECTRAL (1, the
  * Fourier derivative, i.e. the FFT gradient of the paper's code, on
  * periodic axes of at most 4096 points; open axes keep the differences).
- * The spectral form is available to compute_q0, enl_energy, enl_potential
- * and xc_energies, not to the batched calls and plans. */
+ * Every entry point that takes grids accepts the spectral form (batch
+ * plans then need grad_d, where the derivatives are staged). */
 enum { VDW_GRAD_FD = 0, VDW_GRAD_SPECTRAL = 1 };
 
 typedef struct {
@@ -332,8 +332,9 @@ int enl_potential_batched(int32_t B, const vdw_grid *grids, const int64_t *grid_
  * enl_batch_plan_execute: enqueues one evaluation on `stream`: kernel
  *   launches only (no copies, host waits or allocation).  It computes
  *   grad_d (3 planes per density, as compute_q0), q0_d, dq_dn_d, dq_dg_d
- *   (device, packed like n_d; the last three and dEdn_d may be NULL for an
- *   energy-only plan) and writes
+ *   (device, packed like n_d; grad_d, dq_dn_d, dq_dg_d and dEdn_d may be
+ *   NULL for an energy-only plan, grad_d only if no grid takes the
+ *   spectral gradient) and writes
  *     E_d: device, 4B+1 doubles: {E_pair0, E_pairL, E_self} for each
  *          density, then the B retained-point counts, then a flag that is
  *          non-zero when the density held NaN or Inf values.

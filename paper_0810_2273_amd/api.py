@@ -316,7 +316,9 @@ class BatchPlan:
         f64 = dict(dtype=torch.float64, device=device)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.q0 = torch.empty(Gt, **f64)
-        self.grad = torch.empty(3 * Gt, **f64) if potential else None
+        # the spectral gradient is staged in grad, so such plans keep it also for the energy only
+        spectral = any(g.gradient == "spectral" for g in grids)
+        self.grad = torch.empty(3 * Gt, **f64) if (potential or spectral) else None
         self.dq_dn = torch.empty(Gt, **f64) if potential else None
         self.dq_dg = torch.empty(Gt, **f64) if potential else None
         self.dEdn = torch.empty(Gt, **f64) if potential else None

@@ -1338,8 +1338,10 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
     if (t >= Gtot) return;
     const Seg &s = segs[find_seg(segs, B, t, 4)];
     const int64_t o = s.grid_off;
+    // densities with the Fourier derivative have it staged in their grad planes
+    const bool spec = s.spec[0] || s.spec[1] || s.spec[2];
     grad_q0_point(n + o, (long)(t - o), s.nx, s.ny, s.nz, s.px, s.py, s.pz, s.hx, s.hy, s.hz, s.skew ? s.einv : nullptr,
-                  nullptr, (long)s.G, n_cut,
+                  spec ? s.spec : nullptr, (long)s.G, n_cut,
                   grad ? grad + 3 * o : nullptr, q0 + o, dqdn ? dqdn + o : nullptr, dqdg ? dqdg + o : nullptr);
 }
 
@@ -1362,8 +1364,9 @@ struct Plan {
     int mimg[3] = {0, 0, 0};  // image range per axis (0 on open axes)
     bool img = false;
     bool skew = false;  // some density has a skew cell: the general-metric kernels
-    bool spec = false;  // the (single) density takes the Fourier derivative on some axis
+    bool spec = false;  // some density takes the Fourier derivative on some axis
     GridDev g0;         // the first density's grid
+    std::vector<GridDev> gds;  // every density's grid (spectral line kernels)
     bool far = false;   // far image shell (single density)
     FarGeo fg;          // its shell and geometry
     int far_chunks = 1; // j chunks of its row pass (partial sums per chunk)
@@ -1425,6 +1428,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
               Plan *P)
 {
     P->segs.resize(B);
+    P->gds.resize(B);
     P->skew = false;
     P->spec = false;
     int64_t Gtot = 0;
@@ -1467,6 +1471,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             if (g.spec[a]) P->spec = true;
         }
         if (b == 0) P->g0 = g;
+        P->gds[b] = g;
         s.G = g.G;
         s.grid_off = grid_off ? grid_off[b] : 0;
         if (grid_off && grid_off[b + 1] - grid_off[b] != g.G)
@@ -1474,7 +1479,6 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
         Gtot += g.G;
     }
     if (Gtot > ((int64_t)1 << 31) - 1) return fail(VDW_EINVAL, "total grid size exceeds 2^31 - 1");
-    if (P->spec && B > 1) return fail(VDW_EUNSUPPORTED, "the spectral gradient is not available to batched calls");
     auto bound = [&](int64_t BI, int64_t JC) {
         int64_t n = 0;
         for (int b = 0; b < B; ++b) n += items_bound(P->segs[b].G, BI, JC, diag_items(BI, JC));
@@ -1995,22 +1999,18 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
         aa.dEdn = dEdn_d;
         hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((L.Gtot + 255) / 256)), dim3(256), 0, s, aa);
         VDW_HIP(hipGetLastError());
-        if (P.spec)  // a single density (batched calls reject the spectral gradient)
-            for (int a = 0; a < 3; ++a)
-                if (P.g0.spec[a]) {
-                    int rc = launch_spectral_adjoint(P.g0, a, dEdq, dqdg_d, grad_d, dEdn_d, s);
-                    if (rc) return rc;
-                }
+        if (P.spec)  // the transposed Fourier derivative, per density and axis
+            for (int b = 0; b < B; ++b) {
+                const int64_t o = P.segs[b].grid_off;
+                for (int a = 0; a < 3; ++a)
+                    if (P.gds[b].spec[a]) {
+                        int rc = launch_spectral_adjoint(P.gds[b], a, dEdq + o, dqdg_d + o, grad_d + 3 * o,
+                                                         dEdn_d + o, s);
+                        if (rc) return rc;
+                    }
+            }
     }
     return VDW_OK;
-}
-
-bool any_spectral(int B, const vdw_grid *grids)
-{
-    if (!grids || B < 1) return false;
-    for (int b = 0; b < B; ++b)
-        if (grids[b].gradient == VDW_GRAD_SPECTRAL) return true;
-    return false;
 }
 
 thread_local vdw_stats g_stats;
@@ -2134,7 +2134,6 @@ extern "C" int enl_potential_batched(int32_t B, const vdw_grid *grids, const int
     if (!grid_off) return fail(VDW_EINVAL, "grid_off is NULL");
     if (grid_off[0] != 0) return fail(VDW_EINVAL, "grid_off[0] must be 0");
     if (!dEdn_d) return fail(VDW_EINVAL, "dEdn_d is NULL");
-    if (any_spectral(B, grids)) return fail(VDW_EUNSUPPORTED, "the spectral gradient is not available to batched calls");
     return run(B, grids, grid_off, n_d, q0_d, grad_d, dq_dn_d, dq_dg_d, phi_d, phi_f, tp, opts, ws, ws_bytes, dEdn_d,
                E_out, (hipStream_t)stream);
 }
@@ -2169,7 +2168,6 @@ extern "C" int enl_batch_plan_create(int32_t B, const vdw_grid *grids, const int
     if (!grid_off) return fail(VDW_EINVAL, "grid_off is NULL");
     if (B >= 1 && grid_off[0] != 0) return fail(VDW_EINVAL, "grid_off[0] must be 0");
     if (potential != 0 && potential != 1) return fail(VDW_EINVAL, "potential must be 0 or 1");
-    if (any_spectral(B, grids)) return fail(VDW_EUNSUPPORTED, "the spectral gradient is not available to batch plans");
     vdw_batch_plan *p = new (std::nothrow) vdw_batch_plan;
     if (!p) return fail(VDW_ENOMEM, "out of host memory");
     int rc = prepare(B, grids, grid_off, tp, opts, potential, ws, ws_bytes, &p->E);
@@ -2197,8 +2195,20 @@ extern "C" int enl_batch_plan_execute(vdw_batch_plan *plan, const double *n_d, d
     if (!E.fp64 && !phi_f) return fail(VDW_EINVAL, "phi_f is required for VDW_FP32C");
     if (E.adj && (!grad_d || !dq_dn_d || !dq_dg_d || !dEdn_d))
         return fail(VDW_EINVAL, "a potential plan needs grad_d, dq_dn_d, dq_dg_d and dEdn_d");
+    if (E.P.spec && !grad_d) return fail(VDW_EINVAL, "the spectral gradient needs grad_d");
     hipStream_t s = (hipStream_t)stream;
     const Layout &L = E.P.L;
+    if (E.P.spec)
+        // Fourier derivatives per grid step, staged in the densities' grad planes
+        for (int b = 0; b < E.B; ++b) {
+            const GridDev &g = E.P.gds[b];
+            const int64_t o = E.P.segs[b].grid_off;
+            for (int a = 0; a < 3; ++a)
+                if (g.spec[a]) {
+                    int rc = launch_spectral_lines(g, a, n_d + o, grad_d + 3 * o + a * g.G, s);
+                    if (rc) return rc;
+                }
+        }
     hipLaunchKernelGGL(grad_q0_batched_kernel, dim3((unsigned)((L.Gtot + 255) / 256)), dim3(256), 0, s,
                        (const Seg *)(E.ws + L.segs), E.B, L.Gtot, E.n_cut, n_d, grad_d, q0_d, dq_dn_d, dq_dg_d);
     VDW_HIP(hipGetLastError());

@@ -173,9 +173,10 @@ def test_xc_host_side(L, oracle):
 
 
 def test_spectral_gradient_host_validation(L):
-    """The gradient selector is validated, the spectral form needs the
-    gradient planes and a periodic axis of at most 4096 points, and the
-    batched calls and plans refuse it, all before any device work."""
+    """The gradient selector is validated and the spectral form needs the
+    gradient planes and a periodic axis of at most 4096 points, before any
+    device work; the batched calls size a workspace for it (no call here
+    reaches the device)."""
     lib = L.lib()
     dummy = ct.c_void_p(16)  # never dereferenced
     g = L.VdwGrid()
@@ -196,14 +197,11 @@ def test_spectral_gradient_host_validation(L):
     o.n_cut = 1e-5
     o.self_term = 1
     o.table_lds_rows = -1
-    offs = (ct.c_int64 * 2)(0, 512)
-    E = (ct.c_double * 3)()
-    arr = (L.VdwGrid * 1)(g)
-    assert lib.enl_potential_batched(1, arr, offs, dummy, dummy, dummy, dummy, dummy, dummy, None, ct.byref(tp),
-                                     ct.byref(o), dummy, 1 << 30, dummy, E, None) == L.VDW_EUNSUPPORTED
-    plan = ct.c_void_p()
-    assert lib.enl_batch_plan_create(1, arr, offs, ct.byref(tp), ct.byref(o), 1, dummy, 1 << 30, ct.byref(plan),
-                                     None) == L.VDW_EUNSUPPORTED
+    fd = L.VdwGrid.from_buffer_copy(g)
+    fd.gradient = 0
+    lib.enl_batched_workspace_size.restype = ct.c_size_t
+    both = (L.VdwGrid * 2)(g, fd)
+    assert lib.enl_batched_workspace_size(2, both, ct.byref(tp), ct.byref(o)) > 0
     assert lib.xc_workspace_size(ct.byref(g)) > 3 * 512 * 8
 
 

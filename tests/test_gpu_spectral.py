@@ -3,7 +3,8 @@ oracle, whose derivative is an FFT along the axis: gradient and q0 point by
 point; energies and dE/dn element by element (FP64: 1e-12 / 1e-10, FP32C:
 1e-6 / 1e-4), the adjoint including the transposed line operators; the
 exchange-correlation energies; on orthorhombic and skew cells, with even
-and odd periodic axes and an open axis."""
+and odd periodic axes and an open axis; and in a batch with a
+finite-difference density (the batched call and graph plans)."""
 import numpy as np
 import pytest
 
@@ -111,3 +112,56 @@ def test_spectral_xc_energies(V, oracle, k):
     ref = oracle.xc_energies(og, wl.rho, 1e-12)
     for key in ref:
         assert E[key] == pytest.approx(ref[key], rel=1e-12), key
+
+
+def test_spectral_in_batched_calls_and_plans(V, oracle, table):
+    """A batch of a spectral and a finite-difference density (both periodic
+    in x and y, one ring of images): the batched call, a potential plan
+    replayed from its graph and an energy-only plan equal the oracle per
+    density."""
+    import torch
+
+    tp, tab = table
+    wls = [W.random_small(n=(20, 17, 12), h=(0.35, 0.4, 0.3), periodic=(1, 1, 0), seed=83, n_cut=2.2e-3),
+           W.random_small(n=(14, 15, 13), h=(0.4, 0.35, 0.45), periodic=(1, 1, 0), seed=84, n_cut=2.2e-3)]
+    kinds = ("spectral", "fd")
+    grids = [V.Grid(w.n, w.h, w.periodic, gradient=k) for w, k in zip(wls, kinds)]
+    refs = [oracle.evaluate(oracle.Grid(w.n, w.h, w.periodic, gradient=k), w.rho, tab, tp, w.n_cut, (1, 1, 0),
+                            potential=True) for w, k in zip(wls, kinds)]
+    params = V.TableParams(n_D=tp.n_D, n_sigma=tp.n_sigma, D_max=tp.D_max, gl_points=tp.gl_points,
+                           graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0)
+    t64 = torch.tensor(tab, dtype=torch.float64, device="cuda:0").contiguous()
+    gt = V.Table(params, t64, t64.float().contiguous())
+    ns = [torch.tensor(w.rho.reshape(-1), dtype=torch.float64, device="cuda:0") for w in wls]
+    npk, offs = V.pack_batch(grids, ns)
+
+    def check(Eb, vb, etol, vtol, what):
+        for b, ref in enumerate(refs):
+            assert abs(sum(Eb[b]) - ref.E) <= etol * abs(ref.E), (what, b)
+            if vb is not None:
+                seg = vb[offs[b]:offs[b + 1]].cpu().numpy()
+                assert np.linalg.norm(seg - ref.dEdn) <= vtol * np.linalg.norm(ref.dEdn), (what, b)
+
+    qd = V.compute_q0_batched(grids, npk, offs, wls[0].n_cut)
+    for prec in (0, 1):
+        etol, vtol = FP[prec]
+        say(f"spectral batch precision={prec}")
+        Eb, vb = V.enl_potential_batched(grids, npk, offs, qd, gt, V.Opts(n_cut=wls[0].n_cut, image_max=(1, 1, 0),
+                                                                         precision=prec))
+        check(Eb, vb, etol, vtol, "batched")
+    opts = V.Opts(n_cut=wls[0].n_cut, image_max=(1, 1, 0), precision=0)
+    say("spectral plan (graph)")
+    plan = V.BatchPlan(grids, offs, gt, opts)
+    plan.capture(npk)
+    for _ in range(2):
+        plan.replay()
+        torch.cuda.synchronize()
+        check(plan.energies(), plan.dEdn, 1e-12, 1e-10, "plan")
+    plan.close()
+    say("spectral energy-only plan")
+    plan = V.BatchPlan(grids, offs, gt, opts, potential=False)
+    plan.capture(npk)
+    plan.replay()
+    torch.cuda.synchronize()
+    check(plan.energies(), None, 1e-12, None, "energy plan")
+    plan.close()
