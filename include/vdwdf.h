@@ -149,8 +149,7 @@ typedef struct {
                                D; all 0 (or 0 on every periodic axis): none.
                                With a shell: r_cut <= 0, far_max[a] >=
                                image_max[a] on every periodic axis, at most
-                               2^22 lattice vectors, one density per call
-                               (B > 1 gives VDW_EUNSUPPORTED).                */
+                               2^22 lattice vectors.                          */
 } vdw_opts;
 
 /* Thread-local description of the last error (never NULL). */

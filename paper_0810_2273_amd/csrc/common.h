@@ -48,16 +48,18 @@ struct FarGeo {
 };
 int64_t far_table_entries(const FarGeo &g);
 int launch_far_table(const FarGeo &g, double *T, hipStream_t s);
-// Far rows of the N kept points (records in compact order, N read on the
-// device from *nkept, at most nmax), in `chunks` partial sums over as many
+// Far rows of the N kept points of one density (its records start at
+// recs + *first, in compact order; N read on the device from *nkept, at
+// most nmax), in `chunks` partial sums over as many
 // j ranges: part[c nmax + i] = sum_j n_j phi_far(i, j) and (adj)
 // part[(chunks + c) nmax + i] = qscale sum_j n_j d phi_far(i, j) / d a_i, with
 // phi_far = -casym T_ij / (a_i^2 a_j^2 (a_i^2 + a_j^2)), j = i included.
 // T must have fewer than 2^31 entries.
 constexpr int kFarMaxChunks = 16;
 int far_chunks(int64_t nmax);
-int launch_far_rows(const FarGeo &g, int fp64, const void *recs, const int64_t *nkept, int64_t nmax,
-                    const double *T, double casym, double qscale, int chunks, int adj, double *part, hipStream_t s);
+int launch_far_rows(const FarGeo &g, int fp64, const void *recs, const int64_t *nkept, const int64_t *first,
+                    int64_t nmax, const double *T, double casym, double qscale, int chunks, int adj, double *part,
+                    hipStream_t s);
 
 // ---- Fourier derivative along periodic axes (spectral.hip) ----
 // d_a per grid step of every line along `axis` of src (x fastest), written

@@ -71,11 +71,13 @@ constexpr int kFarJ = 4;
 template <typename Rec, bool ADJ>
 __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const Rec *__restrict__ recs,
                                                                const int64_t *__restrict__ nkept,
+                                                               const int64_t *__restrict__ first,
                                                                const double *__restrict__ T, double casym,
                                                                double qscale, int64_t stride,
                                                                double *__restrict__ part)
 {
     const int64_t N = *nkept;
+    recs += *first;
     const int64_t i0 = (int64_t)blockIdx.x * (kFarThreads * kFarIPL);
     if (i0 >= N) return;  // N >= 1 below
     const int C = gridDim.y, c = blockIdx.y;
@@ -170,26 +172,28 @@ int far_chunks(int64_t nmax)
     return C < 1 ? 1 : (int)C;
 }
 
-int launch_far_rows(const FarGeo &g, int fp64, const void *recs, const int64_t *nkept, int64_t nmax,
-                    const double *T, double casym, double qscale, int chunks, int adj, double *part, hipStream_t s)
+int launch_far_rows(const FarGeo &g, int fp64, const void *recs, const int64_t *nkept, const int64_t *first,
+                    int64_t nmax, const double *T, double casym, double qscale, int chunks, int adj, double *part,
+                    hipStream_t s)
 {
     if (nmax < 1) return VDW_OK;
     if (chunks < 1 || chunks > kFarMaxChunks) return fail(VDW_EINVAL, "internal: %d far chunks", chunks);
     const dim3 grid((unsigned)((nmax + kFarThreads * kFarIPL - 1) / (kFarThreads * kFarIPL)), (unsigned)chunks);
     const RecD *rd = (const RecD *)recs;
     const RecF *rf = (const RecF *)recs;
+    const dim3 blk(kFarThreads);
     if (fp64 && adj)
-        hipLaunchKernelGGL((far_rows_kernel<RecD, true>), grid, dim3(kFarThreads), 0, s, g, rd, nkept, T, casym, qscale,
-                           nmax, part);
+        hipLaunchKernelGGL((far_rows_kernel<RecD, true>), grid, blk, 0, s, g, rd, nkept, first, T, casym, qscale, nmax,
+                           part);
     else if (fp64)
-        hipLaunchKernelGGL((far_rows_kernel<RecD, false>), grid, dim3(kFarThreads), 0, s, g, rd, nkept, T, casym,
-                           qscale, nmax, part);
+        hipLaunchKernelGGL((far_rows_kernel<RecD, false>), grid, blk, 0, s, g, rd, nkept, first, T, casym, qscale, nmax,
+                           part);
     else if (adj)
-        hipLaunchKernelGGL((far_rows_kernel<RecF, true>), grid, dim3(kFarThreads), 0, s, g, rf, nkept, T, casym,
-                           qscale, nmax, part);
+        hipLaunchKernelGGL((far_rows_kernel<RecF, true>), grid, blk, 0, s, g, rf, nkept, first, T, casym, qscale, nmax,
+                           part);
     else
-        hipLaunchKernelGGL((far_rows_kernel<RecF, false>), grid, dim3(kFarThreads), 0, s, g, rf, nkept, T, casym,
-                           qscale, nmax, part);
+        hipLaunchKernelGGL((far_rows_kernel<RecF, false>), grid, blk, 0, s, g, rf, nkept, first, T, casym, qscale, nmax,
+                           part);
     VDW_HIP(hipGetLastError());
     return VDW_OK;
 }

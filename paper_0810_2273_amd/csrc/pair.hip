@@ -80,6 +80,9 @@ struct Seg {
     int64_t t_off, T;     // brick-order positions: offset (multiple of kCompactBlock), padded length
     int64_t row_base;     // first entry of this density in the row-offset table
     int64_t slot_base;    // first partial slot of this density
+    int64_t far_tab_off;  // far shell: first entry of this density's lattice-sum table
+    int64_t far_part_off; // far shell: first element of its row partials (2 far_chunks arrays of G)
+    int32_t far_chunks, pad3;
     // filled on the device by scan_kernel
     int64_t N, p_off, item_off, blk_off, nIB, items;
 };
@@ -1064,10 +1067,8 @@ struct FinArgs {
     double *blockE;
     double *dEdn;   // direct part scattered to the grid (potential)
     double *dEdq;   // dE/dq scattered to the grid (potential)
-    const double *far;   // far-shell row partials (compact order): far_chunks S0 arrays, then (potential)
-                         // far_chunks Sq arrays, far_stride apart; or NULL
-    int64_t far_stride;
-    int far_chunks;
+    const double *far;   // far-shell row partials, per density from Seg::far_part_off (compact order):
+                         // far_chunks S0 arrays, then (potential) far_chunks Sq arrays, G apart; or NULL
 };
 
 // phi~(D, 0) and d phi~/dD from the FP64 table (asymptote at D >= D_max).
@@ -1166,9 +1167,10 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
             }
         }
         if (F.far) {
-            for (int c = 0; c < F.far_chunks; ++c) {
-                S0L += F.far[c * F.far_stride + p];
-                if (F.adj) Sq += F.far[(F.far_chunks + c) * F.far_stride + p];
+            const double *fp = F.far + sg.far_part_off;
+            for (int c = 0; c < sg.far_chunks; ++c) {
+                S0L += fp[c * sg.G + lp];
+                if (F.adj) Sq += fp[(sg.far_chunks + c) * sg.G + lp];
             }
         }
         const int64_t g = F.gidx[p];
@@ -1367,9 +1369,9 @@ struct Plan {
     bool spec = false;  // some density takes the Fourier derivative on some axis
     GridDev g0;         // the first density's grid
     std::vector<GridDev> gds;  // every density's grid (spectral line kernels)
-    bool far = false;   // far image shell (single density)
-    FarGeo fg;          // its shell and geometry
-    int far_chunks = 1; // j chunks of its row pass (partial sums per chunk)
+    bool far = false;   // far image shell
+    std::vector<FarGeo> fgs;        // its shell and geometry per density
+    int64_t far_tab = 0, far_part = 0;  // elements of all lattice-sum tables, of all row partials
     int JC = 8192;
     int tpb = kPairThreads;     // pair-kernel workgroup size
     int BI = 2 * kPairThreads;  // i-points per row block (IPL per lane)
@@ -1572,26 +1574,35 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
             if (per[a] && o->far_max[a] > 0) P->far = true;
             if (per[a]) vecs *= 2.0 * o->far_max[a] + 1.0;
         }
+        P->fgs.clear();
+        P->far_tab = P->far_part = 0;
         if (P->far) {
-            if (B > 1) return fail(VDW_EUNSUPPORTED, "the far image shell is not available to batched calls");
             if (o->r_cut > 0.0) return fail(VDW_EINVAL, "the far image shell is defined without a distance cut");
             for (int a = 0; a < 3; ++a)
                 if (per[a] && o->far_max[a] < m[a])
                     return fail(VDW_EINVAL, "far_max[%d] = %d is below image_max[%d] = %d", a, o->far_max[a], a, m[a]);
             if (vecs > 4194304.0) return fail(VDW_EINVAL, "far shell of %.0f lattice vectors (at most 2^22)", vecs);
-            FarGeo &f = P->fg;
-            const Seg &s0 = P->segs[0];
-            f.nx = s0.nx;
-            f.ny = s0.ny;
-            f.nz = s0.nz;
-            for (int a = 0; a < 3; ++a) {
-                f.lo[a] = per[a] ? m[a] : 0;
-                f.hi[a] = per[a] ? o->far_max[a] : 0;
+            P->fgs.resize(B);
+            for (int b = 0; b < B; ++b) {
+                Seg &sb = P->segs[b];
+                FarGeo &f = P->fgs[b];
+                f.nx = sb.nx;
+                f.ny = sb.ny;
+                f.nz = sb.nz;
+                for (int a = 0; a < 3; ++a) {
+                    f.lo[a] = per[a] ? m[a] : 0;
+                    f.hi[a] = per[a] ? o->far_max[a] : 0;
+                }
+                for (int k = 0; k < 9; ++k) f.en[k] = sb.e[k] / sb.hx;
+                const int64_t ne = far_table_entries(f);
+                if (ne >= ((int64_t)1 << 31))
+                    return fail(VDW_EINVAL, "grid %d too large for the far-shell table (2^31 displacements)", b);
+                sb.far_chunks = far_chunks(sb.G);
+                sb.far_tab_off = P->far_tab;
+                sb.far_part_off = P->far_part;
+                P->far_tab += ne;
+                P->far_part += 2 * (int64_t)sb.far_chunks * sb.G;
             }
-            for (int k = 0; k < 9; ++k) f.en[k] = s0.e[k] / s0.hx;
-            if (far_table_entries(f) >= ((int64_t)1 << 31))
-                return fail(VDW_EINVAL, "grid too large for the far-shell table (2^31 displacements)");
-            P->far_chunks = far_chunks(Gtot);
         }
     }
     P->NI = P->NJ = 1 + (P->img ? 1 : 0) + (adj ? 1 : 0);
@@ -1633,9 +1644,9 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     L.dEdq = off;
     if (adj) off = align256(off + Gtot * sizeof(double));
     L.fartab = off;
-    if (P->far) off = align256(off + far_table_entries(P->fg) * sizeof(double));
+    if (P->far) off = align256(off + (size_t)P->far_tab * sizeof(double));
     L.far = off;
-    if (P->far) off = align256(off + 2 * (size_t)P->far_chunks * Gtot * sizeof(double));
+    if (P->far) off = align256(off + (size_t)P->far_part * sizeof(double));
     L.total = off;
     return VDW_OK;
 }
@@ -1917,14 +1928,18 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     VDW_HIP(hipGetLastError());
     double *far = (double *)(w + L.far);
     if (P.far) {
-        // far image shell (a single density): lattice sums, then its rows
+        // far image shell, per density: lattice sums, then its rows (the
+        // kept count and the first record come from the device descriptors)
         double *T = (double *)(w + L.fartab);
         if (evf0) VDW_HIP(hipEventRecord(evf0, s));
-        int rc = launch_far_table(P.fg, T, s);
-        if (rc) return rc;
-        rc = launch_far_rows(P.fg, E.fp64, recs, hdr + HDR_NTOTAL, L.Gtot, T, E.pa.casym, P.segs[0].hx / E.pa.dD2,
-                             P.far_chunks, E.adj, far, s);
-        if (rc) return rc;
+        for (int b = 0; b < B; ++b) {
+            const Seg &sb = P.segs[b];
+            int rc = launch_far_table(P.fgs[b], T + sb.far_tab_off, s);
+            if (rc) return rc;
+            rc = launch_far_rows(P.fgs[b], E.fp64, recs, &segs[b].N, &segs[b].p_off, sb.G, T + sb.far_tab_off,
+                                 E.pa.casym, sb.hx / E.pa.dD2, sb.far_chunks, E.adj, far + sb.far_part_off, s);
+            if (rc) return rc;
+        }
         if (evf1) VDW_HIP(hipEventRecord(evf1, s));
     }
 
@@ -1978,8 +1993,6 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.Dmax = E.Dmax;
     fa.casym = E.casym;
     fa.far = P.far ? far : nullptr;
-    fa.far_stride = L.Gtot;
-    fa.far_chunks = P.far_chunks;
     fa.blockE = blockE;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
@@ -2033,7 +2046,10 @@ void set_stats(const Exec &E, const double *host, float ms, float far_ms)
     g_stats.j_chunks = E.P.JC / 1024;
     g_stats.grid_blocks = E.grid;
     g_stats.diag_items = E.P.ND;
-    g_stats.far_pairs = E.P.far ? (double)retained * (double)retained : 0.0;
+    double far_pairs = 0.0;
+    if (E.P.far)
+        for (int b = 0; b < E.B; ++b) far_pairs += host[3 * E.B + b] * host[3 * E.B + b];
+    g_stats.far_pairs = far_pairs;
     g_stats.far_kernel_ms = far_ms;
 }
 

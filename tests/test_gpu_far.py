@@ -191,7 +191,7 @@ def test_far_shell_approximation_on_the_slab(V):
 def test_far_shell_in_a_graph_plan(V, oracle, tables):
     """A one-density plan with the far shell, recorded as a HIP graph: three
     replays (eager calls in between) equal each other bit for bit and equal
-    the oracle; a batch of two densities with a shell is refused."""
+    the oracle."""
     import torch
 
     name, make, near, far = CASES[0]
@@ -220,8 +220,49 @@ def test_far_shell_in_a_graph_plan(V, oracle, tables):
         else:
             assert E_r == first[0] and torch.equal(v_r, first[1])
     plan.close()
-    with pytest.raises(Exception):
-        V.BatchPlan([g, g], [0, wl.G, 2 * wl.G], table, opts)
+
+
+def test_far_shell_in_batches(V, oracle, tables):
+    """Two periodic densities of different grids and cells (orthorhombic and
+    skew) with the shell: the batched call (FP64 and FP32C) and a graph plan
+    equal the oracle per density."""
+    import torch
+
+    tp, tab = tables[64]
+    table = _gpu_table(V, tp, tab)
+    wls = [W.random_small(n=(14, 12, 16), h=(0.4, 0.4, 0.4), periodic=(1, 1, 0), seed=86, n_cut=2.2e-3),
+           W.random_skew(n=(13, 15, 11), cell=CELL, periodic=(1, 1, 0), seed=87, n_cut=2.2e-3)]
+    near, far = (1, 1, 0), (3, 4, 0)
+    pairs = [_grids(V, oracle, w) for w in wls]
+    grids = [p[0] for p in pairs]
+    refs = [oracle.evaluate(og, w.rho, tab, tp, w.n_cut, near, potential=True, far_max=far)
+            for (_, og), w in zip(pairs, wls)]
+    ns = [torch.tensor(w.rho.reshape(-1), dtype=torch.float64, device="cuda:0") for w in wls]
+    npk, offs = V.pack_batch(grids, ns)
+
+    def check(Eb, vb, etol, vtol, what):
+        for b, ref in enumerate(refs):
+            assert abs(sum(Eb[b]) - ref.E) <= etol * abs(ref.E), (what, b)
+            assert abs(Eb[b][1] - ref.E_pairL) <= etol * abs(ref.E), (what, b)
+            seg = vb[offs[b]:offs[b + 1]].cpu().numpy()
+            assert np.linalg.norm(seg - ref.dEdn) <= vtol * np.linalg.norm(ref.dEdn), (what, b)
+
+    qd = V.compute_q0_batched(grids, npk, offs, wls[0].n_cut)
+    for prec in (0, 1):
+        etol, vtol = FP[prec]
+        say(f"far batch precision={prec}")
+        opts = V.Opts(n_cut=wls[0].n_cut, image_max=near, far_max=far, precision=prec)
+        Eb, vb = V.enl_potential_batched(grids, npk, offs, qd, table, opts)
+        st = V.last_stats()
+        assert st["far_pairs"] == pytest.approx(sum(float(r.q0["keep"].sum()) ** 2 for r in refs))
+        check(Eb, vb, etol, vtol, "batched")
+    say("far batch plan (graph)")
+    plan = V.BatchPlan(grids, offs, table, V.Opts(n_cut=wls[0].n_cut, image_max=near, far_max=far, precision=0))
+    plan.capture(npk)
+    plan.replay()
+    torch.cuda.synchronize()
+    check(plan.energies(), plan.dEdn, 1e-12, 1e-10, "plan")
+    plan.close()
 
 
 def test_far_shell_edge_cases(V, oracle, tables):
