@@ -342,9 +342,37 @@ struct RecOf<double> {
 };
 
 __device__ inline float dsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ inline double dsqrt(double x) { return sqrt(x); }
 __device__ inline float drcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double drcp(double x) { return 1.0 / x; }
+// FP64 reciprocal of a positive normal x: the hardware estimate refined by
+// two Newton steps (each squares the relative error), to about one ulp.
+__device__ inline double drcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+// FP64 square root of a positive normal x from the hardware reciprocal-root
+// estimate y: g = x y and h = y / 2 refined by one Goldschmidt step, then two
+// Newton corrections of g (about one ulp).  x = 0 (only the excluded pair
+// (i, i, 0) of weight zero has it) gives 0, which keeps that pair on the
+// table branch, where every value stays finite.
+__device__ inline double dsqrt(double x)
+{
+    const bool pos = x > 0.0;
+    const double xs = pos ? x : 1.0;
+    const double y = __builtin_amdgcn_rsq(xs);
+    double g = xs * y, h = 0.5 * y;
+    const double e = fma(-g, h, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    double d = fma(-g, g, xs);
+    g = fma(d, h, g);
+    d = fma(-g, g, xs);
+    g = fma(d, h, g);
+    return pos ? g : 0.0;
+}
 __device__ inline float dfract(float x) { return __builtin_amdgcn_fractf(x); }
 __device__ inline double dfract(double x) { return x - floor(x); }
 
