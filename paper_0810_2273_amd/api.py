@@ -78,6 +78,11 @@ class Grid:
 
 @dataclass
 class Opts:
+    """vdw_opts: density cut-off, distance cut and near images (image_max,
+    summed with the table), precision (FP32C or FP64), on-site term, tile
+    shape, Kahan runs, and the far image shell (far_max: the cells beyond
+    image_max up to far_max with the kernel's large-D asymptote, no r_cut)."""
+
     n_cut: float = 1e-5
     r_cut: float = 0.0
     image_max: tuple = (0, 0, 0)
