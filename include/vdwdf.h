@@ -149,7 +149,11 @@ typedef struct {
                                D; all 0 (or 0 on every periodic axis): none.
                                With a shell: r_cut <= 0, far_max[a] >=
                                image_max[a] on every periodic axis, at most
-                               2^22 lattice vectors.                          */
+                               2^22 lattice vectors.  The asymptote is meant
+                               for distant cells: with two near rings it
+                               moves a Xe monolayer's E_pairL by 1e-6 of
+                               itself, with none it replaces the nearest
+                               neighbours' kernel.                            */
 } vdw_opts;
 
 /* Thread-local description of the last error (never NULL). */

@@ -299,3 +299,10 @@ def test_far_shell_edge_cases(V, oracle, tables):
         a, va = run(wl.n_cut, prec)
         b, vb = run(wl.n_cut, prec)
         assert a == b and np.array_equal(va, vb)
+    say("far edge: Kahan-compensated FP32 runs")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    E, v = V.enl_potential(g, n, qd, table, V.Opts(n_cut=wl.n_cut, image_max=(1, 1, 0), far_max=(5, 5, 0),
+                                                   precision=1, kahan=1))
+    ref = oracle.evaluate(og, wl.rho, tab, tp, wl.n_cut, (1, 1, 0), potential=True, far_max=(5, 5, 0))
+    assert abs(sum(E) - ref.E) <= 1e-6 * abs(ref.E)
+    assert np.linalg.norm(v.cpu().numpy() - ref.dEdn) <= 1e-4 * np.linalg.norm(ref.dEdn)
