@@ -175,3 +175,27 @@ def test_far_arguments(oracle):
     b = oracle.evaluate(g, wl.rho, tab, tp, wl.n_cut, (1, 1, 0))
     assert a.E == b.E
     assert math.isfinite(a.E)
+
+
+def test_far_T_square_lattice_closed_form(oracle):
+    """A point and all its images on a square lattice of side L: the r^-6
+    lattice sum is 4 zeta(3) beta(3) / L^6 (zeta(3) Apery's constant,
+    beta(3) = pi^3 / 32); the shell out to 100 rings misses less than 1e-8
+    of it.  On a rectangular lattice of sides L, 2L the sum splits into the
+    two axes' closed forms (2 zeta(6) / L^6 + 2 zeta(6) / (2L)^6) plus the
+    off-axis terms, checked here only for its axis part being a lower
+    bound."""
+    g = oracle.Grid((4, 4, 3), (0.5, 0.5, 0.5), (1, 1, 0))
+    L = 2.0
+    zeta3 = 1.2020569031595942
+    beta3 = math.pi ** 3 / 32.0
+    T0 = float(oracle.far_T(g, (0, 0, 0), (100, 100, 0), [[0, 0, 0]])[0])
+    assert T0 == pytest.approx(4.0 * zeta3 * beta3 / L ** 6, rel=1e-8)
+    rect = oracle.Grid((4, 8, 3), (0.5, 0.5, 0.5), (1, 1, 0))
+    zeta6 = math.pi ** 6 / 945.0
+    T1 = float(oracle.far_T(rect, (0, 0, 0), (100, 100, 0), [[0, 0, 0]])[0])
+    assert T1 > 2.0 * zeta6 / L ** 6 + 2.0 * zeta6 / (2 * L) ** 6
+    # one axis only: the chain sum 2 zeta(6) / L^6
+    chain = oracle.Grid((4, 4, 3), (0.5, 0.5, 0.5), (1, 0, 0))
+    T2 = float(oracle.far_T(chain, (0, 0, 0), (2000, 0, 0), [[0, 0, 0]])[0])
+    assert T2 == pytest.approx(2.0 * zeta6 / L ** 6, rel=1e-12)
