@@ -344,9 +344,14 @@ def main():
         rate64 = pairs * steps64 / dt64
         dE = max(abs(sum(e32) - sum(e64)) / abs(sum(e64)) for e32, e64 in zip(E32, E64))
         dv = float(torch.linalg.norm(v32 - v64) / torch.linalg.norm(v64))
+        ach64 = 0.5 * near_pairs * FLOP_PER_UNORDERED_PAIR / (kms64 * 1e-3) / 1e12
         out["fp64"] = {"value": rate64, "ms_per_step": 1e3 * dt64 / steps64, "kernel_ms": kms64,
                        "speedup_fp32c_over_fp64": value / rate64,
-                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dv_rel_l2": dv}}
+                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dv_rel_l2": dv},
+                       "roofline": {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": ach64 / PEAK_FP64_TFLOPS,
+                                    "kernel": "pair_kernel<double, ADJ, %s>" % (
+                                        "IMG" if a.workload in ("slab", "hexslab", "slabfar") else "noIMG")}}
         if a.workload == "kr":
             for t, s in enumerate(out["scan"]):
                 e_ab, e_a, e_b = (sum(E64[3 * t + k]) for k in range(3))
