@@ -159,7 +159,8 @@ typedef struct {
 /* Thread-local description of the last error (never NULL). */
 const char *vdw_last_error(void);
 
-/* Library version string. */
+/* Library version string.  0.2: vdw_opts.far_max and the far-shell fields
+ * of vdw_stats (the structs grew at their ends). */
 const char *vdw_version(void);
 
 /* ---------------------------------------------------------------------

@@ -132,4 +132,4 @@ int device_info(DevInfo *out)
 
 extern "C" const char *vdw_last_error(void) { return vdw::g_err; }
 
-extern "C" const char *vdw_version(void) { return "vdwdf-mi355x 0.1 (gfx950)"; }
+extern "C" const char *vdw_version(void) { return "vdwdf-mi355x 0.2 (gfx950)"; }
