@@ -26,13 +26,20 @@ struct GridDev {
 
 // Kept point as the pair kernels read it: grid coordinates (exact
 // integers), n, a = q h_x / (2 dD), b = sqrt(n_sigma - 1) a, w = x^2 + y^2
-// + z^2 (exact); FP32 records for VDW_FP32C, FP64 for VDW_FP64.
+// + z^2 (exact); FP32 records for VDW_FP32C, FP64 for VDW_FP64.  `off`
+// holds, as raw bits, the 32-bit value x + (2 n_x - 1)(y + (2 n_y - 1) z),
+// the point's term in the far-shell displacement-table index.
 struct alignas(32) RecF {
-    float x, y, z, n, a, b, w, pad;
+    float x, y, z, n, a, b, w, off;
 };
 struct alignas(64) RecD {
-    double x, y, z, n, a, b, w, pad;
+    double x, y, z, n, a, b, w, off;
 };
+__host__ __device__ inline int rec_off(const RecF &r) { return (int)__builtin_bit_cast(uint32_t, r.off); }
+__host__ __device__ inline int rec_off(const RecD &r)
+{
+    return (int)(uint32_t)__builtin_bit_cast(uint64_t, r.off);
+}
 
 // ---- far image shell (far.hip) ----
 // Shell of one density: lattice vectors m with |m_a| <= hi[a], except those

@@ -83,16 +83,18 @@ __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const R
     const int C = gridDim.y, c = blockIdx.y;
     const int64_t len = (N + C - 1) / C;
     const int64_t j0 = min(N, (int64_t)c * len), j1 = min(N, j0 + len);
-    // table offsets fit 32 bits (the host bounds the table)
+    // table offsets fit 32 bits (the host bounds the table); a record's
+    // `off` is its x + ex (y + ey z)
     const int ex = 2 * g.nx - 1, ey = 2 * g.ny - 1;
+    const int k0 = (g.nx - 1) + ex * ((g.ny - 1) + ey * (g.nz - 1));
     int base[kFarIPL];
     double pi[kFarIPL], g2[kFarIPL], a2[kFarIPL], acc[kFarIPL], accq[kFarIPL];
 #pragma unroll
     for (int p = 0; p < kFarIPL; ++p) {
         const int64_t i = i0 + threadIdx.x + (int64_t)kFarThreads * p;
         const Rec R = recs[i < N ? i : N - 1];
-        // table entry of displacement r_i - r_j is base - offset(j)
-        base[p] = ((int)R.x + g.nx - 1) + ex * (((int)R.y + g.ny - 1) + ey * ((int)R.z + g.nz - 1));
+        // table entry of displacement r_i - r_j is base - off(j)
+        base[p] = rec_off(R) + k0;
         const double a = (double)R.a;
         pi[p] = a * a;
         g2[p] = 2.0 / a;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const R
 #pragma unroll
         for (int u = 0; u < kFarJ; ++u) {
             const Rec J = recs[j + u];
-            oj[u] = (int)J.x + ex * ((int)J.y + ey * (int)J.z);
+            oj[u] = rec_off(J);
             const double aj = (double)J.a;
             pj[u] = aj * aj;
             nj[u] = (double)J.n;
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const R
     }
     for (; j < j1; ++j) {
         const Rec J = recs[j];
-        const int oj = (int)J.x + ex * ((int)J.y + ey * (int)J.z);
+        const int oj = rec_off(J);
         const double aj = (double)J.a;
 #pragma unroll
         for (int p = 0; p < kFarIPL; ++p) term(p, T[(unsigned)(base[p] - oj)], aj * aj, (double)J.n);

@@ -275,8 +275,11 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
         __syncthreads();
     }
     int64_t pos = A.offs[blockIdx.x] + pre[threadIdx.x] - cnt;
+    const uint32_t ex = 2u * (uint32_t)s.nx - 1u, ey = 2u * (uint32_t)s.ny - 1u;
     for (int u = 0; u < 4; ++u) {
         if (!keep[u]) continue;
+        // far-shell table term (wraps harmlessly when no table is built)
+        const uint32_t off = (uint32_t)xs[u] + ex * ((uint32_t)ys[u] + ey * (uint32_t)zs[u]);
         double nn = A.n[gi[u]], q = A.q0[gi[u]];
         double a = q * s.hx * A.inv2dD;
         if (A.fp64) {
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
             r.a = a;
             r.b = a * A.csig;
             r.w = (double)xs[u] * xs[u] + (double)ys[u] * ys[u] + (double)zs[u] * zs[u];
-            r.pad = 0.0;
+            r.off = __builtin_bit_cast(double, (uint64_t)off);
             ((RecD *)A.recs)[pos] = r;
         } else {
             RecF r;
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(kCompactThreads) void scatter_kernel(ScatterArgs A)
             r.a = (float)a;
             r.b = (float)(a * A.csig);
             r.w = (float)((double)xs[u] * xs[u] + (double)ys[u] * ys[u] + (double)zs[u] * zs[u]);
-            r.pad = 0.0f;
+            r.off = __builtin_bit_cast(float, off);
             ((RecF *)A.recs)[pos] = r;
         }
         A.gidx[pos] = (int32_t)gi[u];
