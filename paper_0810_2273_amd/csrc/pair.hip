@@ -377,7 +377,7 @@ __device__ inline double dsqrt(double x)
     return pos ? g : 0.0;
 }
 __device__ inline float dfract(float x) { return __builtin_amdgcn_fractf(x); }
-__device__ inline double dfract(double x) { return x - floor(x); }
+__device__ inline double dfract(double x) { return __builtin_amdgcn_fract(x); }  // x - floor(x), exact for x >= 0
 
 // Rotate a wavefront-wide value by one lane (DPP wave_ror:1): 64 rotations
 // bring every value back to its lane.
