@@ -2,6 +2,7 @@
 pair-kernel timing replaced by a known cost function), and the workspace
 bounds the library's planner reports (no device call is involved)."""
 import json
+import os
 
 import pytest
 
@@ -93,3 +94,17 @@ def test_workspace_bounds_from_the_planner():
     o = V.Opts(n_cut=1e-5, **fixed).c()
     both = int(L.lib().enl_batched_workspace_size(2, arr, ct.byref(tp.c()), ct.byref(o)))
     assert both >= _ws(V, (96, 96, 96), **fixed) + _ws(V, (40, 40, 40), **fixed) - 2 * 4096
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says so,
+    before it imports torch or touches a device."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
