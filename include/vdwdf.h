@@ -152,8 +152,8 @@ typedef struct {
                                2^22 lattice vectors.  The asymptote is meant
                                for distant cells: with two near rings it
                                moves a Xe monolayer's E_pairL by 1e-6 of
-                               itself, with none it replaces the nearest
-                               neighbours' kernel.                            */
+                               itself, with one ring by 2e-4, with none it
+                               replaces the nearest neighbours' kernel.       */
 } vdw_opts;
 
 /* Thread-local description of the last error (never NULL). */

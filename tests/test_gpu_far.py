@@ -181,6 +181,7 @@ def test_far_shell_approximation_on_the_slab(V):
     exact4 = e((4, 4, 0))
     near2 = e((2, 2, 0))
     far4 = e((2, 2, 0), (4, 4, 0))
+    e((1, 1, 0), (4, 4, 0))  # one near ring: printed for the record
     e((2, 2, 0), (32, 32, 0))
     e((3, 3, 0), r_cut=30.0)
     assert abs(far4[1] - exact4[1]) <= 1e-5 * abs(exact4[1])
