@@ -48,7 +48,7 @@ class TableParams(ct.Structure):
     ]
 
 
-def table_params(n_D=1024, n_sigma=32, D_max=48.0, gl_points=8, graded_levels=12, kappa=4.0, A0=64.0, interp=0):
+def table_params(n_D=1024, n_sigma=32, D_max=48.0, gl_points=8, graded_levels=12, kappa=16.0, A0=512.0, interp=0):
     """interp: 0 bilinear, 1 cubic (C1) in D and linear in sigma."""
     return TableParams(n_D, n_sigma, D_max, gl_points, graded_levels, kappa, A0, interp)
 
@@ -83,6 +83,8 @@ def lib():
     L.vo_build_table.restype = ct.c_int
     L.vo_build_table.argtypes = [P(TableParams), dp]
     L.vo_table_nodes.restype = ct.c_int
+    L.vo_phi_many.restype = ct.c_int
+    L.vo_phi_many.argtypes = [ct.c_long, dp, dp, P(TableParams), dp]
     L.vo_table_nodes.argtypes = [P(TableParams), ct.c_long, P(i32), P(i32), dp]
     L.vo_table_interp.restype = d
     L.vo_table_interp.argtypes = [dp, P(TableParams), d, d, dp, dp]
@@ -99,6 +101,11 @@ def lib():
         ct.c_long, P(i32), P(i32), P(i32), dp, dp,
         dp, P(i32), P(i32), P(i32), d,
         dp, P(TableParams), ct.c_long, P(i64), dp, dp, dp,
+    ]
+    L.vo_image_pair_sum.restype = d
+    L.vo_image_pair_sum.argtypes = [
+        ct.c_long, P(i32), P(i32), P(i32), dp, dp,
+        dp, P(i32), P(i32), d, dp, P(TableParams),
     ]
     L.vo_block_sum.restype = d
     L.vo_block_sum.argtypes = [
@@ -181,6 +188,15 @@ def dion_phi(d1, d2, tp) -> float:
 
 def phi_Dsigma(D, sigma, tp) -> float:
     return float(lib().vo_phi_Dsigma(float(D), float(sigma), ct.byref(tp)))
+
+
+def phi_many(D, sigma, tp) -> np.ndarray:
+    """phi(D_t, sigma_t) for arrays of points (threads over the points)."""
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    out = np.zeros(D.shape)
+    lib().vo_phi_many(D.size, _p(D, ct.c_double), _p(sigma, ct.c_double), ct.byref(tp), _p(out, ct.c_double))
+    return out
 
 
 def build_table(tp) -> np.ndarray:
@@ -609,6 +625,41 @@ def pair_rows(grid: Grid, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), r_cut=
         _p(tab, ct.c_double), ct.byref(tp), nrows, rows_p, _p(S0c, ct.c_double), _p(S0i, ct.c_double), _p(Sq, ct.c_double),
     )
     return S0c, S0i, Sq
+
+
+def image_pair_sum(grid: Grid, ix, iy, iz, n, q, tab, tp, m, r_cut=0.0) -> float:
+    """sum_i n_i sum_j n_j phi~ over the pairs of the single image shift m
+    (integer cell multiples; (i, i) skipped for m = 0), with the distance cut.
+    Orthorhombic grids only."""
+    if grid.skew:
+        raise ValueError("image_pair_sum: orthorhombic grids only")
+    ix = np.ascontiguousarray(ix, dtype=np.int32)
+    iy = np.ascontiguousarray(iy, dtype=np.int32)
+    iz = np.ascontiguousarray(iz, dtype=np.int32)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    h = np.asarray(grid.h, dtype=np.float64)
+    gd = np.asarray(grid.n, dtype=np.int32)
+    mm = np.asarray(m, dtype=np.int32)
+    return float(lib().vo_image_pair_sum(
+        len(n), _p(ix, ct.c_int32), _p(iy, ct.c_int32), _p(iz, ct.c_int32), _p(n, ct.c_double), _p(q, ct.c_double),
+        _p(h, ct.c_double), _p(gd, ct.c_int32), _p(mm, ct.c_int32), float(r_cut), _p(tab, ct.c_double),
+        ct.byref(tp)))
+
+
+def half_image_shifts(grid: Grid, image_max):
+    """One of each pair (m, -m) of the nonzero image shifts |m_a| <= image_max[a]
+    on periodic axes: the shifts whose first nonzero component is positive."""
+    lim = [int(image_max[a]) if grid.periodic[a] else 0 for a in range(3)]
+    out = []
+    for a in range(-lim[0], lim[0] + 1):
+        for b in range(-lim[1], lim[1] + 1):
+            for c in range(-lim[2], lim[2] + 1):
+                first = next((v for v in (a, b, c) if v != 0), 0)
+                if first > 0:
+                    out.append((a, b, c))
+    return out
 
 
 def block_sum(grid: Grid, A, B, ix, iy, iz, n, q, tab, tp, image_max=(0, 0, 0), r_cut=0.0):

@@ -273,6 +273,15 @@ int vo_table_nodes(const vo_table_params *p, long count, const int32_t *k, const
     return 0;
 }
 
+/* phi at arbitrary (D, sigma) points, one per loop iteration (refinement
+ * and asymptote checks off the table nodes). */
+int vo_phi_many(long count, const double *D, const double *sigma, const vo_table_params *p, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long t = 0; t < count; ++t) out[t] = vo_phi_Dsigma(D[t], sigma[t], p);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Interpolated kernel.                                                  */
 /* ------------------------------------------------------------------ */
@@ -494,6 +503,42 @@ int vo_pair_rows(long npts, const int32_t *ix, const int32_t *iy, const int32_t 
         Sq[t] = sq;
     }
     return 0;
+}
+
+/* The double sum over the pairs of one image shift L = (m_x n_x h_x,
+ * m_y n_y h_y, m_z n_z h_z):  sum_i n_i sum_j n_j phi~(q_i, q_j, |r_i - r_j - L|)
+ * with the pair kept iff r <= r_cut (when r_cut > 0), (i, i) skipped for L = 0.
+ * The terms of (i, j, L) and (j, i, -L) are equal (phi~ depends on q_i, q_j
+ * through D and delta^2, and the distances agree), so the image part of Eq. (2)
+ * is twice the sum over one half of the nonzero shifts.  Rows are summed in
+ * row order after a parallel loop over them. */
+double vo_image_pair_sum(long npts, const int32_t *ix, const int32_t *iy, const int32_t *iz,
+                         const double *n, const double *q,
+                         const double h[3], const int32_t gdim[3], const int32_t m[3], double r_cut,
+                         const double *tab, const vo_table_params *p)
+{
+    const double Lx = m[0] * gdim[0] * h[0], Ly = m[1] * gdim[1] * h[1], Lz = m[2] * gdim[2] * h[2];
+    const int home = (m[0] == 0 && m[1] == 0 && m[2] == 0);
+    double *row = (double *)malloc(sizeof(double) * (size_t)(npts > 0 ? npts : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < npts; ++i) {
+        double xi = ix[i] * h[0], yi = iy[i] * h[1], zi = iz[i] * h[2];
+        double s = 0.0;
+        for (long j = 0; j < npts; ++j) {
+            if (home && j == i) continue;
+            double dx = xi - ix[j] * h[0] - Lx;
+            double dy = yi - iy[j] * h[1] - Ly;
+            double dz = zi - iz[j] * h[2] - Lz;
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r_cut > 0.0 && r > r_cut) continue;
+            s += n[j] * vo_pair_phi(q[i], q[j], r, tab, p, NULL);
+        }
+        row[i] = n[i] * s;
+    }
+    double total = 0.0;
+    for (long i = 0; i < npts; ++i) total += row[i];
+    free(row);
+    return total;
 }
 
 /* Sum over one explicit set of pairs between two point lists (used by

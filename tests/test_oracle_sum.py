@@ -84,6 +84,15 @@ def test_pair_sum_matches_pure_python_brute_force(oracle, table_cache, periodic,
     assert eL == pytest.approx(bL, rel=1e-13, abs=1e-300)
     if any(image_max):
         assert abs(bL) > 0
+    # the same energies one image shift at a time: the 0th cell, and the images
+    # as twice the sum over one of each pair (m, -m)
+    h0 = 0.5 * dV * dV * oracle.image_pair_sum(g, ix, iy, iz, nS, qS, tab, tp, (0, 0, 0), r_cut)
+    half = oracle.half_image_shifts(g, image_max)
+    full = [m for m in np.ndindex(*(2 * np.asarray(image_max) * np.asarray(periodic) + 1))]
+    assert 2 * len(half) + 1 == len(full)
+    hL = dV * dV * sum(oracle.image_pair_sum(g, ix, iy, iz, nS, qS, tab, tp, m, r_cut) for m in half)
+    assert h0 == pytest.approx(b0, rel=1e-13)
+    assert hL == pytest.approx(bL, rel=1e-13, abs=1e-300)
 
 
 def test_pair_sum_constant_table_closed_form(oracle):
