@@ -14,7 +14,7 @@ import torch
 
 from . import _lib as L
 
-DEFAULT_RULE = dict(gl_points=8, graded_levels=12, kappa=4.0, A0=64.0)
+DEFAULT_RULE = dict(gl_points=8, graded_levels=12, kappa=16.0, A0=512.0)
 
 
 @dataclass
@@ -26,8 +26,8 @@ class TableParams:
     D_max: float = 48.0
     gl_points: int = 8
     graded_levels: int = 12
-    kappa: float = 4.0
-    A0: float = 64.0
+    kappa: float = 16.0
+    A0: float = 512.0
     interp: int = 0  # 0 bilinear, 1 cubic (C1) in D and linear in sigma (FP64 form)
 
     def c(self) -> L.VdwTableParams:

@@ -8,11 +8,13 @@
 // max(d1, d2)).  The integrand
 //   a^2 b^2 W(a,b) T(nu1(a), nu1(b), nu2(a), nu2(b))
 // is evaluated as
-//   (P_a U_b + P_b U_a - 3 U_a U_b) * S (c_a c_b + s5 s6) / (s1 s2 c_a c_b s5 s6)
+//   2 (U_b (P_a - 3 U_a) + P_b U_a) * S (c_a c_b + s5 s6) / (2 s1 s2 c_a c_b s5 s6)
 // with P = x sin x, U = (sin x - x cos x)/x, c = nu1 + nu2, S = c_a + c_b,
 // s1 = nu1(a)+nu1(b), s2 = nu2(a)+nu2(b), s5 = nu1(a)+nu2(b), s6 = nu2(a)+nu1(b):
 // the factors 2 of a^2 b^2 W and 1/2 of T cancel, and T's four reciprocals
-// become one division because w+y = c_a and x+z = c_b.
+// become one (w+y = c_a and x+z = c_b), taken as the hardware estimate with
+// two Newton steps.  The integrand is symmetric in (a, b): the double sum
+// visits the pairs j >= i only.
 #include <math.h>
 
 #include <vector>
@@ -24,7 +26,7 @@ namespace vdw {
 namespace {
 
 constexpr int kTableThreads = 256;
-constexpr int kChunk = 256;  // j-nodes staged in LDS per pass
+constexpr int kChunk = kTableThreads;  // j-nodes staged in LDS per pass, one per thread
 
 struct TableArgs {
     int nD, nS, ng, K;
@@ -137,9 +139,38 @@ __device__ inline Node make_node(const TableArgs &a, int idx, double d1, double 
     return nd;
 }
 
+// Points per axis of the rule at (d1, d2): the graded panels and the panels of
+// width pi/2 up to A, the smallest odd multiple of pi/2 >= max(A0, kappa max(d1, d2)).
+__host__ __device__ inline int64_t rule_points(int ng, int K, double kappa, double A0, double d1, double d2)
+{
+    const double w0 = 0.5 * 3.14159265358979323846;
+    double target = fmax(A0, kappa * fmax(d1, d2));
+    int64_t m = (int64_t)ceil((target / w0 - 1.0) * 0.5);
+    if (m < 0) m = 0;
+    while ((2.0 * m + 1.0) * w0 < target) ++m;
+    return (K + 1 + 2 * m) * (int64_t)ng;
+}
+
+// FP64 reciprocal of a positive normal x: the hardware estimate and two Newton
+// steps (each squares the relative error), about one ulp.
+__device__ inline double rcp_refined(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// One workgroup per table node.  The integrand is symmetric under a <-> b, so
+// only the blocks on and above the diagonal are visited: the 256 threads take
+// one i-node each (a block of 256 consecutive nodes, set up once), and the
+// j-nodes of each later chunk of 256 are staged in LDS with their weight folded
+// into P and U.  Pairs j > i count twice, j = i once.  Padding nodes carry zero
+// weight and finite values.
 __global__ __launch_bounds__(kTableThreads) void phi_node_kernel(TableArgs a, double *__restrict__ phi)
 {
-    __shared__ double sP[kChunk], sU[kChunk], s1[kChunk], s2[kChunk], sc[kChunk], sw[kChunk];
+    __shared__ double s1[kChunk], s2[kChunk], sc[kChunk], swP[kChunk], swU[kChunk];
     __shared__ double red[kTableThreads];
 
     const int node = blockIdx.x;
@@ -147,48 +178,60 @@ __global__ __launch_bounds__(kTableThreads) void phi_node_kernel(TableArgs a, do
     const double D = k * a.dD;
     const double delta = sqrt((double)l / (double)(a.nS - 1));
     const double d1 = D * (1.0 + delta), d2 = D * (1.0 - delta);
-    const double w0 = 0.5 * 3.14159265358979323846;
-    double target = fmax(a.A0, a.kappa * fmax(d1, d2));
-    int m = (int)ceil((target / w0 - 1.0) * 0.5);
-    if (m < 0) m = 0;
-    while ((2.0 * m + 1.0) * w0 < target) ++m;
-    const int n = (a.K + 1 + 2 * m) * a.ng;
+    const int n = (int)rule_points(a.ng, a.K, a.kappa, a.A0, d1, d2);
+    const int nb = (n + kChunk - 1) / kChunk;
+    const int tid = threadIdx.x;
 
     double acc = 0.0;
-    for (int j0 = 0; j0 < n; j0 += kChunk) {
-        int jn = min(kChunk, n - j0);
-        for (int t = threadIdx.x; t < jn; t += kTableThreads) {
-            Node nd = make_node(a, j0 + t, d1, d2);
-            sP[t] = nd.P;
-            sU[t] = nd.U;
-            s1[t] = nd.n1;
-            s2[t] = nd.n2;
-            sc[t] = nd.c;
-            sw[t] = nd.w;
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += kTableThreads) {
-            Node ni = make_node(a, i, d1, d2);
-            double row = 0.0;
-            for (int j = 0; j < jn; ++j) {
-                double cc = ni.c * sc[j];
-                double s56 = (ni.n1 + s2[j]) * (ni.n2 + s1[j]);
-                double num = (ni.c + sc[j]) * (cc + s56);
-                double den = (ni.n1 + s1[j]) * (ni.n2 + s2[j]) * cc * s56;
-                double wpart = ni.P * sU[j] + sP[j] * ni.U - 3.0 * ni.U * sU[j];
-                row += sw[j] * wpart * (num / den);
+    for (int ib = 0; ib < nb; ++ib) {
+        const int i = ib * kChunk + tid;
+        Node ni = make_node(a, min(i, n - 1), d1, d2);
+        const double wi = (i < n) ? ni.w : 0.0;
+        const double Ai = ni.P - 3.0 * ni.U;  // a^2 b^2 W / 2 = U_j (P_i - 3 U_i) + P_j U_i
+        double off = 0.0, diag = 0.0;
+        for (int jb = ib; jb < nb; ++jb) {
+            __syncthreads();
+            {
+                const int j = jb * kChunk + tid;
+                Node nj = make_node(a, min(j, n - 1), d1, d2);
+                const double wj = (j < n) ? nj.w : 0.0;
+                s1[tid] = nj.n1;
+                s2[tid] = nj.n2;
+                sc[tid] = nj.c;
+                swP[tid] = wj * nj.P;
+                swU[tid] = wj * nj.U;
             }
-            acc += ni.w * row;
+            __syncthreads();
+            if (jb == ib) {
+                for (int t = 0; t < kChunk; ++t) {
+                    const double cc = ni.c * sc[t];
+                    const double s56 = (ni.n1 + s2[t]) * (ni.n2 + s1[t]);
+                    const double num = (ni.c + sc[t]) * (cc + s56);
+                    const double den = (ni.n1 + s1[t]) * (ni.n2 + s2[t]) * cc * s56;
+                    const double wpart = fma(swU[t], Ai, swP[t] * ni.U);
+                    const double f = (t > tid) ? 2.0 : (t == tid ? 1.0 : 0.0);
+                    diag = fma(f * wpart * num, rcp_refined(den), diag);
+                }
+            } else {
+                for (int t = 0; t < kChunk; ++t) {
+                    const double cc = ni.c * sc[t];
+                    const double s56 = (ni.n1 + s2[t]) * (ni.n2 + s1[t]);
+                    const double num = (ni.c + sc[t]) * (cc + s56);
+                    const double den = (ni.n1 + s1[t]) * (ni.n2 + s2[t]) * cc * s56;
+                    const double wpart = fma(swU[t], Ai, swP[t] * ni.U);
+                    off = fma(wpart * num, rcp_refined(den), off);
+                }
+            }
         }
-        __syncthreads();
+        acc = fma(wi, fma(2.0, off, diag), acc);
     }
-    red[threadIdx.x] = acc;
+    red[tid] = acc;
     __syncthreads();
     for (int s = kTableThreads / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        if (tid < s) red[tid] += red[tid + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         const double pi = 3.14159265358979323846;
         phi[(long)k * a.nS + l] = 2.0 / (pi * pi) * red[0];
     }
@@ -244,6 +287,11 @@ extern "C" int build_phi_table(const vdw_table_params *tp, double *phi_d, float 
 {
     int rc = vdw::validate_table(tp);
     if (rc) return rc;
+    // the largest node count per axis is at D_max, delta = 1 (d1 = 2 D_max, d2 = 0)
+    const int64_t npts = vdw::rule_points(tp->gl_points, tp->graded_levels, tp->kappa, tp->A0, 2.0 * tp->D_max, 0.0);
+    if (npts > ((int64_t)1 << 20))
+        return vdw::fail(VDW_EINVAL, "the quadrature rule needs %lld points per axis at D_max (at most 2^20)",
+                         (long long)npts);
     if (!phi_d) return vdw::fail(VDW_EINVAL, "phi_d is NULL");
     hipStream_t s = (hipStream_t)stream;
     rc = vdw::launch_phi_table(tp, phi_d, phi_f, s);
