@@ -297,6 +297,27 @@ int enl_potential(const vdw_grid *grid, const double *n_d, const double *q0_d, c
                   const vdw_table_params *tp, const vdw_opts *opts, void *ws, size_t ws_bytes,
                   double *dEdn_d, double *E_out, void *stream);
 
+/* ---------------------------------------------------------------------
+ * enl_potential_noalloc -- enl_potential for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and results, with
+ * the workspace taken from a static device array of the library instead of
+ * the caller (64 MiB on every GPU the library runs on, held until the
+ * process ends; enough for grids of about 40^3 points in either precision).
+ * Nothing is allocated on the device; the first call on a device looks up
+ * that device's copy of the array.  Every call on one GPU shares the array:
+ * calls that overlap on one GPU (other host threads, other streams) race and
+ * give wrong results, so the caller serialises them.  The array keeps the
+ * last call's contents; each call clears what it needs.
+ *   Arguments as enl_potential, without ws and ws_bytes.
+ * Errors as enl_potential; VDW_EWORKSPACE when the grid and options need
+ * more than the static array (enl_workspace_size() > 64 MiB).
+ * ------------------------------------------------------------------- */
+int enl_potential_noalloc(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *grad_d,
+                          const double *dq_dn_d, const double *dq_dg_d, const double *phi_d, const float *phi_f,
+                          const vdw_table_params *tp, const vdw_opts *opts, double *dEdn_d, double *E_out,
+                          void *stream);
+
 /* Bytes of workspace enl_potential_batched needs for these B grids. */
 size_t enl_batched_workspace_size(int32_t B, const vdw_grid *grids, const vdw_table_params *tp,
                                   const vdw_opts *opts);

@@ -25,7 +25,7 @@ EXPORTS = (
     "vdw_last_error", "vdw_version", "build_phi_table", "compute_q0", "enl_workspace_size", "enl_energy",
     "enl_potential", "enl_batched_workspace_size", "enl_potential_batched", "vdw_last_stats", "vdw_set_timing",
     "enl_batch_plan_create", "enl_batch_plan_execute", "enl_batch_plan_capture", "enl_batch_plan_replay",
-    "enl_batch_plan_destroy", "xc_workspace_size", "xc_energies", "vdw_recombine",
+    "enl_batch_plan_destroy", "xc_workspace_size", "xc_energies", "vdw_recombine", "enl_potential_noalloc",
 )
 
 
@@ -92,6 +92,9 @@ def lib():
     L.enl_potential.restype = ct.c_int
     L.enl_potential.argtypes = [P(VdwGrid), vp, vp, vp, vp, vp, vp, vp, P(VdwTableParams), P(VdwOpts), vp, sz,
                                 vp, P(d), vp]
+    L.enl_potential_noalloc.restype = ct.c_int
+    L.enl_potential_noalloc.argtypes = [P(VdwGrid), vp, vp, vp, vp, vp, vp, vp, P(VdwTableParams), P(VdwOpts),
+                                        vp, P(d), vp]
     L.enl_potential_batched.restype = ct.c_int
     L.enl_potential_batched.argtypes = [i32, P(VdwGrid), P(ct.c_int64), vp, vp, vp, vp, vp, vp, vp,
                                         P(VdwTableParams), P(VdwOpts), vp, sz, vp, P(d), vp]

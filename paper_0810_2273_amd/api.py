@@ -222,6 +222,22 @@ def enl_potential(grid: Grid, n: torch.Tensor, qd: dict, table: Table, opts: Opt
     return (float(E[0]), float(E[1]), float(E[2])), dEdn
 
 
+def enl_potential_noalloc(grid: Grid, n: torch.Tensor, qd: dict, table: Table, opts: Opts, stream=None):
+    """enl_potential on the library's static device scratch (no workspace is
+    allocated; grids up to the scratch size, calls on one GPU serialised by
+    the caller).  The dE/dn output is allocated here by torch; a caller that
+    cannot allocate passes its own buffer through the C ABI."""
+    _f64(n, "n")
+    tp, g, o = table.params.c(), grid.c(), opts.c()
+    dEdn = torch.empty(grid.G, dtype=torch.float64, device=n.device)
+    E = (ct.c_double * 3)()
+    L.check(L.lib().enl_potential_noalloc(ct.byref(g), _ptr(n), _ptr(qd["q0"]), _ptr(qd["grad"]),
+                                          _ptr(qd["dq_dn"]), _ptr(qd["dq_dg"]), _ptr(table.phi64),
+                                          _ptr(table.phi32), ct.byref(tp), ct.byref(o), _ptr(dEdn), E,
+                                          _stream(stream)))
+    return (float(E[0]), float(E[1]), float(E[2])), dEdn
+
+
 XC_TERMS = ("Ex_lda", "Ec_lda", "Ex_pbe", "Ec_pbe", "Ex_revpbe")
 
 

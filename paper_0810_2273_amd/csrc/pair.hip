@@ -38,6 +38,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -2134,6 +2135,72 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     return VDW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// the entry point without allocation: its workspace is `scratch`, a static
+// device array of every GPU the library runs on
+// ---------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;  // 64 MiB (grids up to about 40^3 points)
+constexpr int kMaxDevices = 64;
+
+// In host code `scratch` names a host-side stand-in: kernels and copies take
+// the device address that scratch_ptr() looks up per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device (set on first use)
+
+int scratch_ptr(void **out)
+{
+    int dev = 0;
+    VDW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(VDW_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(VDW_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return VDW_OK;
+}
+
+// enl_potential on the static scratch.  The host-side plan is kept per
+// thread, so repeated calls reuse its storage; no timing events.
+int run_noalloc(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *grad_d,
+                const double *dqdn_d, const double *dqdg_d, const double *phi_d, const float *phi_f,
+                const vdw_table_params *tp, const vdw_opts *o, double *dEdn_d, double *E_out, hipStream_t s)
+{
+    if (!n_d || !q0_d || !phi_d || !E_out || !dEdn_d) return fail(VDW_EINVAL, "NULL argument");
+    if (o && o->precision == VDW_FP32C && !phi_f) return fail(VDW_EINVAL, "phi_f is required for VDW_FP32C");
+    if (!grad_d || !dqdn_d || !dqdg_d) return fail(VDW_EINVAL, "grad_d, dq_dn_d and dq_dg_d are required");
+    void *ws = nullptr;
+    int rc = scratch_ptr(&ws);
+    if (rc) return rc;
+    static thread_local Exec E;
+    rc = prepare(1, grid, nullptr, tp, o, 1, ws, kScratchBytes, &E);
+    if (rc == VDW_EWORKSPACE)
+        return fail(VDW_EWORKSPACE,
+                    "enl_potential_noalloc: this grid and these options need %zu bytes of scratch; the library's "
+                    "static scratch holds %zu (use enl_potential with a workspace)",
+                    E.P.L.total, kScratchBytes);
+    if (rc) return rc;
+    rc = upload(E, s);
+    if (rc) return rc;
+    double *res = (double *)(E.ws + E.P.L.res);
+    rc = enqueue(E, n_d, q0_d, grad_d, dqdn_d, dqdg_d, phi_d, phi_f, dEdn_d, res, s, nullptr, nullptr);
+    if (rc) return rc;
+    double host[5];
+    VDW_HIP(hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, s));
+    VDW_HIP(hipStreamSynchronize(s));
+    if (host[4] != 0.0) return fail(VDW_ENONFINITE, "the density holds NaN or Inf values");
+    for (int k = 0; k < 3; ++k) E_out[k] = host[k];
+    set_stats(E, host, 0.0f, 0.0f);
+    return VDW_OK;
+}
+
 }  // namespace
 
 }  // namespace vdw
@@ -2170,6 +2237,15 @@ extern "C" int enl_potential(const vdw_grid *grid, const double *n_d, const doub
     if (!dEdn_d) return fail(VDW_EINVAL, "dEdn_d is NULL");
     return run(1, grid, nullptr, n_d, q0_d, grad_d, dq_dn_d, dq_dg_d, phi_d, phi_f, tp, opts, ws, ws_bytes, dEdn_d,
                E_out, (hipStream_t)stream);
+}
+
+extern "C" int enl_potential_noalloc(const vdw_grid *grid, const double *n_d, const double *q0_d,
+                                     const double *grad_d, const double *dq_dn_d, const double *dq_dg_d,
+                                     const double *phi_d, const float *phi_f, const vdw_table_params *tp,
+                                     const vdw_opts *opts, double *dEdn_d, double *E_out, void *stream)
+{
+    return run_noalloc(grid, n_d, q0_d, grad_d, dq_dn_d, dq_dg_d, phi_d, phi_f, tp, opts, dEdn_d, E_out,
+                       (hipStream_t)stream);
 }
 
 extern "C" int enl_potential_batched(int32_t B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d,
