@@ -59,6 +59,11 @@ PEAK_FP64_TFLOPS = 78.6
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
 TRAFFIC_BYTES = {"kr": (5047278.3125 * 2.0 + 6034241.21875) * 1024}
+# The metric's accuracy gate: FP32C against the FP64 form (and against the
+# oracle's full-size energies where they are stored).
+GATE_DE_REL = 1e-6
+GATE_DV_REL = 1e-4
+GOLDEN = os.path.join(ROOT, "tests", "golden", "fullsize_energies.json")
 
 
 def parse():
@@ -314,6 +319,11 @@ def main():
     }
     if a.workload in PROFILE_COUNTERS:
         out["roofline"]["counters"] = PROFILE_COUNTERS[a.workload]
+    if any(wl.periodic):
+        out["image_window"] = {"reach_bohr": st["image_reach"], "covers_r_cut": st["image_cut_covered"],
+                               "q0_min": st["q0_min"]}
+        if far_pairs:
+            out["image_window"]["far_D_min_bound"] = st["far_D_min"]
     tot = [sum(e[k] for e in E32) for k in range(3)]
     out["energy_ha"] = {"E_pair0": tot[0], "E_pairL": tot[1], "E_self": tot[2], "E": sum(tot)}
     if a.workload == "kr":
@@ -345,9 +355,16 @@ def main():
         dE = max(abs(sum(e32) - sum(e64)) / abs(sum(e64)) for e32, e64 in zip(E32, E64))
         dv = float(torch.linalg.norm(v32 - v64) / torch.linalg.norm(v64))
         ach64 = 0.5 * near_pairs * FLOP_PER_UNORDERED_PAIR / (kms64 * 1e-3) / 1e12
+        passed = bool(dE <= GATE_DE_REL and dv <= GATE_DV_REL)
+        if not passed:
+            print(f"# WARNING: FP32C misses the accuracy gate against FP64 (|dE|/|E| = {dE:.2e}, "
+                  f"|dv|/|v| = {dv:.2e}; tolerances {GATE_DE_REL}, {GATE_DV_REL}): the rate does not count",
+                  file=sys.stderr, flush=True)
+        out["accuracy_gate"] = {"dE_rel_tol": GATE_DE_REL, "dv_rel_tol": GATE_DV_REL, "passed": passed,
+                                "against": "GPU FP64 form, every density of the step"}
         out["fp64"] = {"value": rate64, "ms_per_step": 1e3 * dt64 / steps64, "kernel_ms": kms64,
                        "speedup_fp32c_over_fp64": value / rate64,
-                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dv_rel_l2": dv},
+                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dv_rel_l2": dv, "within_gate": passed},
                        "roofline": {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                     "frac": ach64 / PEAK_FP64_TFLOPS,
                                     "kernel": "pair_kernel<double, ADJ, %s>" % (
@@ -356,6 +373,24 @@ def main():
             for t, s in enumerate(out["scan"]):
                 e_ab, e_a, e_b = (sum(E64[3 * t + k]) for k in range(3))
                 s["E_nl_minus_E_inf_fp64"] = e_ab - e_a - e_b
+            gate = oracle_gate(W, E32, E64)
+            if gate is not None:
+                out["accuracy_gate"]["oracle"] = gate
+                if not gate["passed"]:
+                    out["accuracy_gate"]["passed"] = False
+                    print("# WARNING: the R = 7 densities miss the oracle gate", file=sys.stderr, flush=True)
+        if a.kahan == 0 and a.workload in ("kr", "kr1", "slab"):
+            # the Kahan-compensated form (kahan = 1) beside the headline: rate and accuracy on the same step
+            a.kahan = 1
+            plans.clear()
+            steps_k = max(1, a.steps // 2)
+            dtk, Ek, vk, kmsk, _ = timed(V.VDW_FP32C, steps_k, 1)
+            a.kahan = 0
+            dEk = max(abs(sum(ek) - sum(e64)) / abs(sum(e64)) for ek, e64 in zip(Ek, E64))
+            dvk = float(torch.linalg.norm(vk - v64) / torch.linalg.norm(v64))
+            out["kahan"] = {"value": pairs * steps_k / dtk, "ms_per_step": 1e3 * dtk / steps_k, "kernel_ms": kmsk,
+                            "vs_fp64": {"dE_rel_max": dEk, "dv_rel_l2": dvk,
+                                        "within_gate": bool(dEk <= GATE_DE_REL and dvk <= GATE_DV_REL)}}
     if batched and a.workload != "dimer24":
         # energy only (no adjoint sums, no dE/dn): the same step as a plan without the potential
         p = V.BatchPlan(grids, offs, table, opts(main_prec), potential=False)
@@ -416,6 +451,33 @@ def main():
                          "i.e. 7.8e6 ordered pairs/s")
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
+
+
+def oracle_gate(W, E32, E64):
+    """The R = 7 dimer and its two atoms of the scan (densities 3, 4, 5)
+    against the oracle's full-size energies (tests/golden/fullsize_energies.json,
+    written by tests/golden/make_fullsize_energies.py with the default table
+    rule, the rule this benchmark's table is built with): |dE| per component
+    over |E| of the density, FP32C and FP64.  None when the file is absent."""
+    if not os.path.exists(GOLDEN):
+        return None
+    gold = json.load(open(GOLDEN)).get("workloads", {})
+    res = {"source": os.path.relpath(GOLDEN, ROOT), "tol_fp32c": GATE_DE_REL, "tol_fp64": 1e-11}
+    ok = True
+    t = list(W.KR_SEPARATIONS).index(7.0)
+    for k, which in enumerate(("both", "A", "B")):
+        ref = gold.get(f"kr_dimer_R7_{which}")
+        if ref is None:
+            continue
+        Eref = (ref["E_pair0"], ref["E_pairL"], ref["E_self"])
+        scale = abs(sum(Eref))
+        for name, E, tol in (("fp32c", E32, GATE_DE_REL), ("fp64", E64, 1e-11)):
+            e = E[3 * t + k]
+            d = max(abs(x - y) for x, y in zip(e, Eref)) / scale
+            res[f"R7_{which}_{name}_dE_rel"] = d
+            ok = ok and d <= tol
+    res["passed"] = ok
+    return res
 
 
 def cpu_baseline(wl, rows):

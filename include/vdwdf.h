@@ -164,7 +164,8 @@ typedef struct {
 const char *vdw_last_error(void);
 
 /* Library version string.  0.2: vdw_opts.far_max and the far-shell fields
- * of vdw_stats (the structs grew at their ends). */
+ * of vdw_stats; 0.3: the image-window fields of vdw_stats (the structs grew
+ * at their ends). */
 const char *vdw_version(void);
 
 /* ---------------------------------------------------------------------
@@ -412,9 +413,36 @@ typedef struct {
     int32_t diag_items;     /* diagonal work items per row block */
     double  far_pairs;      /* ordered pairs (i, j) of the far-shell pass (N^2), or 0 */
     float   far_kernel_ms;  /* far-shell table and row kernels (timing on), or 0 */
+    /* since 0.3: how far the near images reach and how far the far shell is
+     * from the table (Sec. 3 periodic repetition; Sec. 7 asymptote) */
+    double  image_reach;    /* every pair (i, j, L) closer than this (bohr) is
+                               summed by the near images (vdw_image_window);
+                               +inf without periodic axes */
+    int32_t image_cut_covered; /* 1: image_reach > r_cut, every pair inside
+                               the cut is summed; 0: the image window leaves
+                               out pairs inside the cut (or truncates the sum
+                               when there is no cut); -1: no periodic axis */
+    double  q0_min;         /* smallest q0 over the kept points (1/bohr) */
+    double  far_D_min;      /* a lower bound on D = (q_i + q_j) r / 2 over the
+                               far-shell pairs, q0_min * image_reach (0 without
+                               a far shell): the shell's asymptote is exact only
+                               where D >= D_max, so far_D_min < D_max marks the
+                               shell as an approximation */
 } vdw_stats;
 
 int vdw_last_stats(vdw_stats *out);
+
+/* The near image window of a grid and options, from the geometry alone
+ * (Sec. 3, periodic repetition): *reach (bohr, may be NULL) is a distance
+ * below which every pair (i, j, L) has its image L inside |m_a| <=
+ * image_max[a] on the periodic axes: min over periodic axes of
+ * (image_max[a] + 1/n[a]) times the spacing of the lattice planes along a
+ * (|det(cell)| / |cell[b] x cell[c]|; exact on orthorhombic cells), +inf
+ * without periodic axes.  *covers (may be NULL) is image_cut_covered of
+ * vdw_stats.  Host only; no device work.
+ * Errors: VDW_EINVAL (bad grid, NULL opts, negative image_max, both outputs
+ * NULL). */
+int vdw_image_window(const vdw_grid *grid, const vdw_opts *opts, double *reach, int32_t *covers);
 void vdw_set_timing(int32_t on);
 
 #ifdef __cplusplus

@@ -26,6 +26,7 @@ EXPORTS = (
     "enl_potential", "enl_batched_workspace_size", "enl_potential_batched", "vdw_last_stats", "vdw_set_timing",
     "enl_batch_plan_create", "enl_batch_plan_execute", "enl_batch_plan_capture", "enl_batch_plan_replay",
     "enl_batch_plan_destroy", "xc_workspace_size", "xc_energies", "vdw_recombine", "enl_potential_noalloc",
+    "vdw_image_window",
 )
 
 
@@ -56,6 +57,8 @@ class VdwStats(ct.Structure):
         ("retained", ct.c_int64), ("pairs", ct.c_double), ("pair_kernel_ms", ct.c_float),
         ("lds_rows", ct.c_int32), ("block_threads", ct.c_int32), ("j_chunks", ct.c_int32), ("grid_blocks", ct.c_int32),
         ("diag_items", ct.c_int32), ("far_pairs", ct.c_double), ("far_kernel_ms", ct.c_float),
+        ("image_reach", ct.c_double), ("image_cut_covered", ct.c_int32), ("q0_min", ct.c_double),
+        ("far_D_min", ct.c_double),
     ]
 
 
@@ -92,6 +95,8 @@ def lib():
     L.enl_potential.restype = ct.c_int
     L.enl_potential.argtypes = [P(VdwGrid), vp, vp, vp, vp, vp, vp, vp, P(VdwTableParams), P(VdwOpts), vp, sz,
                                 vp, P(d), vp]
+    L.vdw_image_window.restype = ct.c_int
+    L.vdw_image_window.argtypes = [P(VdwGrid), P(VdwOpts), P(d), P(i32)]
     L.enl_potential_noalloc.restype = ct.c_int
     L.enl_potential_noalloc.argtypes = [P(VdwGrid), vp, vp, vp, vp, vp, vp, vp, P(VdwTableParams), P(VdwOpts),
                                         vp, P(d), vp]

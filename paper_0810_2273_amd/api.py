@@ -8,6 +8,7 @@ functions raise.
 from __future__ import annotations
 
 import ctypes as ct
+import threading
 from dataclasses import dataclass, field
 
 import torch
@@ -174,15 +175,30 @@ def compute_q0(grid: Grid, n: torch.Tensor, n_cut: float, derivatives: bool = Tr
 
 
 _WS = {}
+_WS_LOCK = threading.Lock()
 
 
-def _workspace(nbytes: int, device) -> torch.Tensor:
-    key = (str(device),)
-    ws = _WS.get(key)
-    if ws is None or ws.numel() < nbytes:
-        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
-        _WS[key] = ws
-    return ws
+def _workspace(nbytes: int, device, stream=None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """The device workspace of one call: the caller's `ws` if given (checked
+    for size), else a cached buffer per (device, stream).  Calls on different
+    streams then never share scratch (the C ABI requires that); calls on one
+    stream are ordered by it, and a buffer replaced by a larger one is freed
+    through torch's stream-ordered allocator."""
+    if ws is not None:
+        if ws.dtype != torch.uint8 or not ws.is_contiguous() or ws.device != torch.device(device):
+            raise TypeError("ws must be a contiguous uint8 tensor on the density's device")
+        if ws.numel() < nbytes:
+            raise L.VdwError(L.VDW_EWORKSPACE, f"workspace has {ws.numel()} bytes, needs {nbytes}")
+        return ws
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (str(torch.device(device)), int(s.cuda_stream))
+    with _WS_LOCK:
+        buf = _WS.get(key)
+        if buf is None or buf.numel() < nbytes:
+            with torch.cuda.stream(s):
+                buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            _WS[key] = buf
+    return buf
 
 
 def enl_workspace_size(grid: Grid, table: Table | TableParams, opts: Opts) -> int:
@@ -191,29 +207,31 @@ def enl_workspace_size(grid: Grid, table: Table | TableParams, opts: Opts) -> in
     return int(L.lib().enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)))
 
 
-def enl_energy(grid: Grid, n: torch.Tensor, q0: torch.Tensor, table: Table, opts: Opts, stream=None):
-    """(E_pair0, E_pairL, E_self) in Hartree."""
+def enl_energy(grid: Grid, n: torch.Tensor, q0: torch.Tensor, table: Table, opts: Opts, stream=None, ws=None):
+    """(E_pair0, E_pairL, E_self) in Hartree.  `ws`: an optional caller-owned
+    uint8 workspace of at least enl_workspace_size bytes."""
     _f64(n, "n")
     _f64(q0, "q0")
     tp, g, o = table.params.c(), grid.c(), opts.c()
     nbytes = int(L.lib().enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)))
     if nbytes == 0:
         raise L.VdwError(L.VDW_EINVAL, "invalid arguments for enl_workspace_size")
-    ws = _workspace(nbytes, n.device)
+    ws = _workspace(nbytes, n.device, stream, ws)
     E = (ct.c_double * 3)()
     L.check(L.lib().enl_energy(ct.byref(g), _ptr(n), _ptr(q0), _ptr(table.phi64), _ptr(table.phi32),
                                ct.byref(tp), ct.byref(o), _ptr(ws), ws.numel(), E, _stream(stream)))
     return float(E[0]), float(E[1]), float(E[2])
 
 
-def enl_potential(grid: Grid, n: torch.Tensor, qd: dict, table: Table, opts: Opts, stream=None):
-    """Energies and dE/dn on every grid point (the potential is dE/dn / dV)."""
+def enl_potential(grid: Grid, n: torch.Tensor, qd: dict, table: Table, opts: Opts, stream=None, ws=None):
+    """Energies and dE/dn on every grid point (the potential is dE/dn / dV).
+    `ws`: an optional caller-owned uint8 workspace (enl_workspace_size bytes)."""
     _f64(n, "n")
     tp, g, o = table.params.c(), grid.c(), opts.c()
     nbytes = int(L.lib().enl_workspace_size(ct.byref(g), ct.byref(tp), ct.byref(o)))
     if nbytes == 0:
         raise L.VdwError(L.VDW_EINVAL, "invalid arguments for enl_workspace_size")
-    ws = _workspace(nbytes, n.device)
+    ws = _workspace(nbytes, n.device, stream, ws)
     dEdn = torch.empty(grid.G, dtype=torch.float64, device=n.device)
     E = (ct.c_double * 3)()
     L.check(L.lib().enl_potential(ct.byref(g), _ptr(n), _ptr(qd["q0"]), _ptr(qd["grad"]), _ptr(qd["dq_dn"]),
@@ -254,7 +272,7 @@ def xc_energies(grid: Grid, n: torch.Tensor, n_floor: float = 1e-12, stream=None
     nbytes = int(L.lib().xc_workspace_size(ct.byref(g)))
     if nbytes == 0:
         raise L.VdwError(L.VDW_EINVAL, "invalid grid for xc_workspace_size")
-    ws = _workspace(nbytes, n.device)
+    ws = _workspace(nbytes, n.device, stream)
     E = (ct.c_double * 5)()
     L.check(L.lib().xc_energies(ct.byref(g), _ptr(n), float(n_floor), _ptr(ws), ws.numel(), E, _stream(stream)))
     return dict(zip(XC_TERMS, (float(x) for x in E)))
@@ -295,7 +313,8 @@ def compute_q0_batched(grids, n_packed: torch.Tensor, offs, n_cut: float, stream
     return out
 
 
-def enl_potential_batched(grids, n_packed: torch.Tensor, offs, qd: dict, table: Table, opts: Opts, stream=None):
+def enl_potential_batched(grids, n_packed: torch.Tensor, offs, qd: dict, table: Table, opts: Opts, stream=None,
+                          ws=None):
     """enl_potential for a packed batch in one pass; returns ([(E0, EL, Es)] per density, dEdn packed)."""
     B = len(grids)
     garr = (L.VdwGrid * B)(*[g.c() for g in grids])
@@ -304,7 +323,7 @@ def enl_potential_batched(grids, n_packed: torch.Tensor, offs, qd: dict, table: 
     nbytes = int(L.lib().enl_batched_workspace_size(B, garr, ct.byref(tp), ct.byref(o)))
     if nbytes == 0:
         raise L.VdwError(L.VDW_EINVAL, "invalid arguments for enl_batched_workspace_size")
-    ws = _workspace(nbytes, n_packed.device)
+    ws = _workspace(nbytes, n_packed.device, stream, ws)
     dEdn = torch.empty(offs[-1], dtype=torch.float64, device=n_packed.device)
     E = (ct.c_double * (3 * B))()
     L.check(L.lib().enl_potential_batched(B, garr, off, _ptr(n_packed), _ptr(qd["q0"]), _ptr(qd["grad"]),
@@ -396,7 +415,21 @@ def last_stats() -> dict:
     L.check(L.lib().vdw_last_stats(ct.byref(s)))
     return dict(retained=s.retained, pairs=s.pairs, pair_kernel_ms=s.pair_kernel_ms, lds_rows=s.lds_rows,
                 block_threads=s.block_threads, j_chunks=s.j_chunks, grid_blocks=s.grid_blocks,
-                diag_items=s.diag_items, far_pairs=s.far_pairs, far_kernel_ms=s.far_kernel_ms)
+                diag_items=s.diag_items, far_pairs=s.far_pairs, far_kernel_ms=s.far_kernel_ms,
+                image_reach=s.image_reach, image_cut_covered=s.image_cut_covered, q0_min=s.q0_min,
+                far_D_min=s.far_D_min)
+
+
+def image_window(grid: Grid, opts: Opts):
+    """(reach in bohr, covers) of the near image window (vdw_image_window):
+    every pair closer than reach is summed; covers is 1 when reach > r_cut,
+    0 when the window leaves out pairs inside the cut (or there is no cut),
+    -1 without periodic axes.  Host only."""
+    g, o = grid.c(), opts.c()
+    reach = ct.c_double()
+    covers = ct.c_int32()
+    L.check(L.lib().vdw_image_window(ct.byref(g), ct.byref(o), ct.byref(reach), ct.byref(covers)))
+    return float(reach.value), int(covers.value)
 
 
 def set_timing(on: bool):

@@ -92,6 +92,8 @@ int fail(int code, const char *fmt, ...);
 
 int validate_grid(const vdw_grid *g, GridDev *out);
 int validate_table(const vdw_table_params *tp);
+double image_reach(const vdw_grid *g, const int32_t *image_max);
+int image_cut_covered(const vdw_grid *g, const vdw_opts *o, double reach);
 
 // Device properties cached per device.
 struct DevInfo {

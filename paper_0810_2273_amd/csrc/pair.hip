@@ -57,11 +57,12 @@ constexpr int kRun = 64;              // j-terms per FP32 run before the FP64 ca
 constexpr int kLdsBytes = 160 * 1024; // LDS of one gfx950 workgroup
 
 // Table elements a pair workgroup of NW wavefronts keeps in LDS, next to
-// its j-side reduction buffer (NW x NJ x 64) and the work-item slot.
+// its j-side reduction buffer (NW x 64 doubles, one accumulator array at a
+// time) and the work-item slot.
 template <typename R>
-constexpr int tab_elems(int NJ, int NW)
+constexpr int tab_elems(int NW)
 {
-    return (int)((kLdsBytes - NW * NJ * 64 * sizeof(R) - 64) / sizeof(R));
+    return (int)((kLdsBytes - NW * 64 * sizeof(double) - 64) / sizeof(R));
 }
 
 enum { HDR_ITEMS = 0, HDR_NTOTAL = 1, HDR_BLKS = 2, HDR_WORDS = 8 };
@@ -119,6 +120,12 @@ __global__ void zero_words_kernel(int64_t *__restrict__ a, int n)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) a[t] = 0;
+}
+
+__global__ void max_words_kernel(unsigned long long *__restrict__ a, int n)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = ~0ull;
 }
 
 // Brick-order position -> grid coordinates of one segment; false if outside.
@@ -800,16 +807,17 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                                                             const int64_t *__restrict__ hdr, int *__restrict__ counter,
                                                             const R *__restrict__ tabg, const int *__restrict__ imgs,
                                                             const int64_t *__restrict__ rowoff,
-                                                            double *__restrict__ ipart, R *__restrict__ jpart)
+                                                            double *__restrict__ ipart, double *__restrict__ jpart)
 {
     using Rec = typename RecOf<R>::T;
     constexpr int NJc = 1 + (IMG ? 1 : 0) + (ADJ ? 1 : 0);
     constexpr bool NORM = GEO == kCubic && sizeof(R) == 4;
     // static LDS: the table rows (K x S, row stride S = n_sigma + 1), the
-    // j-side sums of one tile from every wavefront, the work-item slot
+    // j-side sums of one tile from every wavefront (one accumulator array at
+    // a time, FP64), the work-item slot
     constexpr int NW = TPB / 64;  // wavefronts of the workgroup
-    __shared__ __align__(16) R tab[tab_elems<R>(NJc, NW)];
-    __shared__ R red[NW * NJc * 64];
+    __shared__ __align__(16) R tab[tab_elems<R>(NW)];
+    __shared__ double red[NW * 64];
     __shared__ int s_item_v;
     int *s_item = &s_item_v;
 
@@ -999,7 +1007,9 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                     jb6[4] = uniform(wave_min<R>(q[2]));
                     jb6[5] = uniform(wave_max<R>(q[2]));
                 }
-                R jSc = 0, jSL = 0, jSq = 0;
+                // j-side sums of the tile over the image shifts, carried in
+                // FP64 after every 64-step ring (as the i side)
+                double jSc = 0.0, jSL = 0.0, jSq = 0.0;
                 for (int L = 0; L < nimg; ++L) {
                     R lx = 0, ly = 0, lz = 0;
                     bool home = true, masked = prune;  // no cut: every tile unmasked
@@ -1041,22 +1051,24 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                         else SL[p] += (double)acc[p];
                         if (ADJ) Sq[p] += (double)accq[p];
                     }
-                    if (home) jSc += accj;
-                    else jSL += accj;
-                    if (ADJ) jSq += accqj;
+                    if (home) jSc += (double)accj;
+                    else jSL += (double)accj;
+                    if (ADJ) jSq += (double)accqj;
                 }
-                // j-side sums of the tile: 16 wavefronts in a fixed order
-                red[(w * NJc + 0) * 64 + lane] = jSc;
-                if (IMG) red[(w * NJc + iS0L) * 64 + lane] = jSL;
-                if (ADJ) red[(w * NJc + iSq) * 64 + lane] = jSq;
-                __syncthreads();
-                if (threadIdx.x < NJc * 64) {
-                    const int a = threadIdx.x >> 6, jl = threadIdx.x & 63;
-                    R sum = 0;
-                    for (int v = 0; v < NW; ++v) sum += red[(v * NJc + a) * 64 + jl];
-                    if (t0 + jl < J1) jpart[a * A.jstride + slot * A.JC + (t0 + jl - J0)] = sum;
+                // j-side sums of the tile: the wavefronts' FP64 partials added
+                // in a fixed order, one accumulator array at a time
+#pragma unroll
+                for (int a = 0; a < NJc; ++a) {
+                    red[w * 64 + lane] = (a == 0) ? jSc : (IMG && a == iS0L) ? jSL : jSq;
+                    __syncthreads();
+                    if (threadIdx.x < 64) {
+                        double sum = 0.0;
+                        for (int v = 0; v < NW; ++v) sum += red[v * 64 + threadIdx.x];
+                        if (t0 + (int)threadIdx.x < J1)
+                            jpart[a * A.jstride + slot * A.JC + (t0 + threadIdx.x - J0)] = sum;
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
         const int64_t base = slot * BI + w * (64 * IPL) + lane;
@@ -1083,8 +1095,7 @@ struct FinArgs {
     const int64_t *hdr;
     const int64_t *rowoff;
     const double *ipart;
-    const void *jpart;
-    int jfp64;
+    const double *jpart;
     int64_t istride, jstride;
     int JC, BI, ND, NI, NJ;
     int img, adj, self_term;
@@ -1097,6 +1108,7 @@ struct FinArgs {
     int nD, nS;
     double dD, Dmax, casym;
     double *blockE;
+    unsigned long long *qmin;  // per density: bits of the smallest q0 of a kept point (positive doubles order as integers)
     double *dEdn;   // direct part scattered to the grid (potential)
     double *dEdq;   // dE/dq scattered to the grid (potential)
     const double *far;   // far-shell row partials, per density from Seg::far_part_off (compact order):
@@ -1162,12 +1174,14 @@ __device__ inline double voxel_phi(const FinArgs &F, const double *e, double q, 
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
 {
     __shared__ double r0[kFinThreads], r1[kFinThreads], r2[kFinThreads];
+    __shared__ unsigned long long r3[kFinThreads];
     const int64_t blk = blockIdx.x;
     if (blk >= F.hdr[HDR_BLKS]) return;
     const int b = find_seg(F.segs, F.B, blk, 3);
     const Seg &sg = F.segs[b];
     const int64_t lp = (blk - sg.blk_off) * kFinThreads + threadIdx.x;
     double e0 = 0.0, eL = 0.0, es = 0.0;
+    unsigned long long qb = ~0ull;
     if (lp < sg.N) {
         const int64_t p = sg.p_off + lp;
         double S0c = 0.0, S0L = 0.0, Sq = 0.0;
@@ -1186,17 +1200,9 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
             const int64_t off = lp - (I + 1) * F.BI;
             const int64_t cc = off / F.JC;
             const int64_t k = (sg.slot_base + ro[I] + F.ND + cc) * F.JC + (off - cc * F.JC);
-            if (F.jfp64) {
-                const double *jp = (const double *)F.jpart;
-                S0c += jp[k];
-                if (F.img) S0L += jp[iL * F.jstride + k];
-                if (F.adj) Sq += jp[iq * F.jstride + k] * (sg.hx / (2.0 * F.dD));
-            } else {
-                const float *jp = (const float *)F.jpart;
-                S0c += (double)jp[k];
-                if (F.img) S0L += (double)jp[iL * F.jstride + k];
-                if (F.adj) Sq += (double)jp[iq * F.jstride + k] * (sg.hx / (2.0 * F.dD));
-            }
+            S0c += F.jpart[k];
+            if (F.img) S0L += F.jpart[iL * F.jstride + k];
+            if (F.adj) Sq += F.jpart[iq * F.jstride + k] * (sg.hx / (2.0 * F.dD));
         }
         if (F.far) {
             const double *fp = F.far + sg.far_part_off;
@@ -1207,6 +1213,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         }
         const int64_t g = F.gidx[p];
         const double nn = F.n[g], q = F.q0[g];
+        qb = (unsigned long long)__builtin_bit_cast(uint64_t, q);
         const double rho_s = cbrt(3.0 * sg.dV / (4.0 * 3.14159265358979323846)) * exp(-1.0 / 3.0);
         double Phi = 0.0, dPhi = 0.0;
         if (F.self_term == 2) {
@@ -1229,12 +1236,14 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
     r0[threadIdx.x] = e0;
     r1[threadIdx.x] = eL;
     r2[threadIdx.x] = es;
+    r3[threadIdx.x] = qb;
     __syncthreads();
     for (int st = kFinThreads / 2; st > 0; st >>= 1) {
         if (threadIdx.x < st) {
             r0[threadIdx.x] += r0[threadIdx.x + st];
             r1[threadIdx.x] += r1[threadIdx.x + st];
             r2[threadIdx.x] += r2[threadIdx.x + st];
+            r3[threadIdx.x] = min(r3[threadIdx.x], r3[threadIdx.x + st]);
         }
         __syncthreads();
     }
@@ -1242,6 +1251,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         F.blockE[3 * blk + 0] = r0[0];
         F.blockE[3 * blk + 1] = r1[0];
         F.blockE[3 * blk + 2] = r2[0];
+        atomicMin(F.qmin + b, r3[0]);
     }
 }
 
@@ -1384,8 +1394,8 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, dEdq, fartab, far,
-        total;
+    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, qmin, dEdq, fartab,
+        far, total;
     int64_t nblocks, slots, rows, fin_blocks, Gtot;
 };
 
@@ -1645,7 +1655,6 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     L.rows = rows;
     L.fin_blocks = fin;
     L.Gtot = Gtot;
-    const size_t esz = fp64 ? sizeof(double) : sizeof(float);
     size_t off = 0;
     L.hdr = off;
     off = align256(off + HDR_WORDS * sizeof(int64_t));
@@ -1668,11 +1677,13 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     L.ipart = off;
     off = align256(off + (size_t)P->NI * slots * BI * sizeof(double));
     L.jpart = off;
-    off = align256(off + (size_t)P->NJ * slots * JC * esz);
+    off = align256(off + (size_t)P->NJ * slots * JC * sizeof(double));
     L.blockE = off;
     off = align256(off + 3 * fin * sizeof(double));
     L.res = off;
     off = align256(off + (4 * B + 1) * sizeof(double));
+    L.qmin = off;
+    off = align256(off + B * sizeof(uint64_t));
     L.dEdq = off;
     if (adj) off = align256(off + Gtot * sizeof(double));
     L.fartab = off;
@@ -1720,7 +1731,7 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
     if (attr_only) return VDW_OK;
     hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, GEO, IPL, TPB>), dim3(grid), dim3(TPB), lds, s, a,
                        (const typename RecOf<R>::T *)p.recs, p.segs, p.hdr, p.counter, (const R *)p.tabg, p.imgs,
-                       p.rowoff, p.ipart, (R *)p.jpart);
+                       p.rowoff, p.ipart, (double *)p.jpart);
     VDW_HIP(hipGetLastError());
     return VDW_OK;
 }
@@ -1795,6 +1806,8 @@ struct Exec {
     size_t lds = 0;
     double n_cut = 0.0, dD = 0.0, Dmax = 0.0, casym = 0.0;
     int nD = 0;
+    double reach = 0.0;  // near image window: every pair closer than this is summed (smallest over the densities)
+    int covered = -1;    // image_cut_covered of the window (the smallest over the densities)
     PairArgs pa;
     char *ws = nullptr;
 };
@@ -1830,6 +1843,13 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     if (rc) return rc;
     const Plan &P = E->P;
     if (ws_bytes < P.L.total) return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
+    E->reach = INFINITY;
+    E->covered = 1;
+    for (int b = 0; b < B; ++b) {
+        const double r = image_reach(&grids[b], o->image_max);
+        E->reach = fmin(E->reach, r);
+        E->covered = min(E->covered, image_cut_covered(&grids[b], o, r));
+    }
     E->ws = (char *)ws;
     const int S = tp->n_sigma + 1;
     if (dev.lds_per_block < (size_t)kLdsBytes)
@@ -1837,7 +1857,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
                     dev.lds_per_block);
     // table rows that fit in the kernel's static LDS next to its reduction buffer
     E->tpb = P.tpb;
-    const int cap = E->fp64 ? tab_elems<double>(P.NJ, E->tpb / 64) : tab_elems<float>(P.NJ, E->tpb / 64);
+    const int cap = E->fp64 ? tab_elems<double>(E->tpb / 64) : tab_elems<float>(E->tpb / 64);
     int K = cap / S;
     if (o->table_lds_rows >= 0 && o->table_lds_rows < K) K = o->table_lds_rows;
     if (K > tp->n_D) K = tp->n_D;
@@ -1927,9 +1947,11 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     void *jpart = w + L.jpart;
     double *blockE = (double *)(w + L.blockE);
     double *dEdq = (double *)(w + L.dEdq);
+    unsigned long long *qmin = (unsigned long long *)(w + L.qmin);
 
     // counter and flag live in 64-bit words right after the header
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, hdr, HDR_WORDS);
+    hipLaunchKernelGGL(max_words_kernel, dim3((B + 255) / 256), dim3(256), 0, s, qmin, B);
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, (int64_t *)counter, 1);
     hipLaunchKernelGGL(zero_words_kernel, dim3(1), dim3(64), 0, s, (int64_t *)flag, 1);
     VDW_HIP(hipGetLastError());
@@ -1999,8 +2021,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.hdr = hdr;
     fa.rowoff = rowoff;
     fa.ipart = ipart;
-    fa.jpart = jpart;
-    fa.jfp64 = E.fp64;
+    fa.jpart = (const double *)jpart;
     fa.istride = E.pa.istride;
     fa.jstride = E.pa.jstride;
     fa.JC = P.JC;
@@ -2026,6 +2047,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.casym = E.casym;
     fa.far = P.far ? far : nullptr;
     fa.blockE = blockE;
+    fa.qmin = qmin;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
     if (L.fin_blocks > 0)
@@ -2061,7 +2083,7 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
 thread_local vdw_stats g_stats;
 thread_local int g_timing = 0;
 
-void set_stats(const Exec &E, const double *host, float ms, float far_ms)
+void set_stats(const Exec &E, const double *host, const uint64_t *qmin, float ms, float far_ms)
 {
     double pairs = 0.0;
     int64_t retained = 0;
@@ -2083,6 +2105,14 @@ void set_stats(const Exec &E, const double *host, float ms, float far_ms)
         for (int b = 0; b < E.B; ++b) far_pairs += host[3 * E.B + b] * host[3 * E.B + b];
     g_stats.far_pairs = far_pairs;
     g_stats.far_kernel_ms = far_ms;
+    double q0_min = INFINITY;
+    for (int b = 0; b < E.B; ++b)
+        if (host[3 * E.B + b] > 0.0) q0_min = fmin(q0_min, __builtin_bit_cast(double, qmin[b]));
+    g_stats.image_reach = E.reach;
+    g_stats.image_cut_covered = E.covered;
+    g_stats.q0_min = retained > 0 ? q0_min : 0.0;
+    // far-shell pairs are at least the window's reach apart, and D >= min(q) r
+    g_stats.far_D_min = (E.P.far && retained > 0) ? q0_min * E.reach : 0.0;
 }
 
 // The whole pipeline for B densities, energies read back to the host.
@@ -2112,8 +2142,11 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     double *res = (double *)(E.ws + E.P.L.res);
     rc = enqueue(E, n_d, q0_d, grad_d, dqdn_d, dqdg_d, phi_d, phi_f, dEdn_d, res, s, ev0, ev1, evf0, evf1);
     std::vector<double> host(4 * B + 1);
+    std::vector<uint64_t> qmin(B);
     if (!rc) {
         hipError_t e = hipMemcpyAsync(host.data(), res, host.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(qmin.data(), E.ws + E.P.L.qmin, B * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = fail(VDW_EHIP, "reading the energies back: %s", hipGetErrorString(e));
     }
@@ -2131,7 +2164,7 @@ int run(int B, const vdw_grid *grids, const int64_t *grid_off, const double *n_d
     if (rc) return rc;
     if (host[4 * B] != 0.0) return fail(VDW_ENONFINITE, "the density holds NaN or Inf values");
     for (int k = 0; k < 3 * B; ++k) E_out[k] = host[k];
-    set_stats(E, host.data(), ms, far_ms);
+    set_stats(E, host.data(), qmin.data(), ms, far_ms);
     return VDW_OK;
 }
 
@@ -2193,11 +2226,13 @@ int run_noalloc(const vdw_grid *grid, const double *n_d, const double *q0_d, con
     rc = enqueue(E, n_d, q0_d, grad_d, dqdn_d, dqdg_d, phi_d, phi_f, dEdn_d, res, s, nullptr, nullptr);
     if (rc) return rc;
     double host[5];
+    uint64_t qmin[1];
     VDW_HIP(hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, s));
+    VDW_HIP(hipMemcpyAsync(qmin, E.ws + E.P.L.qmin, sizeof(qmin), hipMemcpyDeviceToHost, s));
     VDW_HIP(hipStreamSynchronize(s));
     if (host[4] != 0.0) return fail(VDW_ENONFINITE, "the density holds NaN or Inf values");
     for (int k = 0; k < 3; ++k) E_out[k] = host[k];
-    set_stats(E, host, 0.0f, 0.0f);
+    set_stats(E, host, qmin, 0.0f, 0.0f);
     return VDW_OK;
 }
 

@@ -94,6 +94,41 @@ int validate_grid(const vdw_grid *g, GridDev *out)
     return VDW_OK;
 }
 
+// Reach of the near image window: every pair (i, j, L) whose distance is below
+// it has its L inside |m_a| <= image_max[a] (periodic axes).  A lattice vector
+// outside the window has |m_a| >= image_max[a] + 1 on some periodic axis a,
+// while two grid points of the cell differ by at most (n_a - 1)/n_a in the
+// fractional coordinate along a, so the pair's separation has a fractional
+// component of at least image_max[a] + 1/n_a there, i.e. a length of at least
+// (image_max[a] + 1/n_a) times the spacing of the lattice planes along a,
+// |det(cell)| / |cell[b] x cell[c]|.  Exact on orthorhombic cells.  +inf
+// without periodic axes.
+double image_reach(const vdw_grid *g, const int32_t *image_max)
+{
+    double reach = INFINITY;
+    const double(*c)[3] = g->cell;
+    const double det = c[0][0] * (c[1][1] * c[2][2] - c[1][2] * c[2][1]) -
+                       c[0][1] * (c[1][0] * c[2][2] - c[1][2] * c[2][0]) +
+                       c[0][2] * (c[1][0] * c[2][1] - c[1][1] * c[2][0]);
+    for (int a = 0; a < 3; ++a) {
+        if (!g->periodic[a]) continue;
+        const double *u = c[(a + 1) % 3], *v = c[(a + 2) % 3];
+        const double x = u[1] * v[2] - u[2] * v[1], y = u[2] * v[0] - u[0] * v[2], z = u[0] * v[1] - u[1] * v[0];
+        const double height = fabs(det) / sqrt(x * x + y * y + z * z);
+        reach = fmin(reach, (image_max[a] + 1.0 / g->n[a]) * height);
+    }
+    return reach;
+}
+
+// 1: the near images hold every pair closer than opts->r_cut (> 0); 0: the
+// window leaves out some pair inside the cut, or there is no cut on a
+// periodic grid (the window then truncates the sum); -1: no periodic axis.
+int image_cut_covered(const vdw_grid *g, const vdw_opts *o, double reach)
+{
+    if (!g->periodic[0] && !g->periodic[1] && !g->periodic[2]) return -1;
+    return (o->r_cut > 0.0 && reach > o->r_cut) ? 1 : 0;
+}
+
 int validate_table(const vdw_table_params *tp)
 {
     if (!tp) return fail(VDW_EINVAL, "table params are NULL");
@@ -132,4 +167,18 @@ int device_info(DevInfo *out)
 
 extern "C" const char *vdw_last_error(void) { return vdw::g_err; }
 
-extern "C" const char *vdw_version(void) { return "vdwdf-mi355x 0.2 (gfx950)"; }
+extern "C" const char *vdw_version(void) { return "vdwdf-mi355x 0.3 (gfx950)"; }
+
+extern "C" int vdw_image_window(const vdw_grid *grid, const vdw_opts *opts, double *reach, int32_t *covers)
+{
+    int rc = vdw::validate_grid(grid, nullptr);
+    if (rc) return rc;
+    if (!opts) return vdw::fail(VDW_EINVAL, "opts is NULL");
+    if (!reach && !covers) return vdw::fail(VDW_EINVAL, "reach and covers are both NULL");
+    for (int a = 0; a < 3; ++a)
+        if (opts->image_max[a] < 0) return vdw::fail(VDW_EINVAL, "image_max must be >= 0");
+    const double r = vdw::image_reach(grid, opts->image_max);
+    if (reach) *reach = r;
+    if (covers) *covers = vdw::image_cut_covered(grid, opts, r);
+    return VDW_OK;
+}
