@@ -401,9 +401,17 @@ __device__ inline double wrot(double x)
     return __builtin_bit_cast(double, v);
 }
 
+// Two f16 values in one register (the x, y grid coordinates of the cubic
+// squared distance, exact as f16 for |value| <= 2048), rotated as one.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+__device__ inline half2v wrot(half2v x)
+{
+    return __builtin_bit_cast(half2v, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x13C, 0xF, 0xF, true));
+}
+
 template <typename R>
 struct PairK {
-    R tDmax, tDlds, tSclamp, csig, c4, casym, wy, wz;
+    R tDmax, tDlds, tSclamp, csig, c4, rc4, casym, wy, wz;  // rc4 = 1 / c4
     R m01, m02, m12;  // skew cells (see Seg)
     R en[9];
     int S, nS, K;
@@ -583,20 +591,22 @@ __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *
     }
 }
 
-// FP32 form: ci = 2 csig a_i, so u = ci / s - csig in one FMA (cj unused).
+// FP32 form: ci = 2 csig a_i, so u = ci / s - csig in one FMA; the j point
+// comes as ej = 4 csig a_j and the i point also as ei = 4 csig a_i, which
+// puts the factor 4 csig of the sigma slope into the q-derivative products:
+// dq_i = gD r + Z ej, dq_j = gD r - Z ei, Z = gS (u / s) / s.
 // The LDS rows are read and interpolated for every pair; one compare
 // (t_D >= K - 1) sends the pairs beyond them to a second pass with the
 // global table or the asymptote, which few pairs take.
 template <bool ADJ, bool JSIDE, int NSIG>
 __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *tab, const float *__restrict__ tabg,
-                                          float m, float ai, float ci, float aj, float cj, float &phi, float &dqi,
+                                          float m, float ai, float ci, float ej, float ei, float &phi, float &dqi,
                                           float &dqj)
 {
-    (void)cj;
     const int S = NSIG > 0 ? NSIG + 1 : k.S;
     const int nS = NSIG > 0 ? NSIG : k.nS;
     const float r = dsqrt(m);
-    const float s = ai + aj;
+    const float s = fmaf(ej, k.rc4, ai);
     const float tD = s * r;
     const float inv = drcp(s);
     const float u = fmaf(ci, inv, -k.csig);
@@ -610,16 +620,16 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
     // the clamped LDS read is always in bounds
     const int kl = min(kk, k.K - 2);
     const float *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
-    bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, k.c4, ai, aj, phi, dqi, dqj);
+    bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
     if (tD >= k.tDlds) {
         if (tD < k.tDmax) {
             // global rows have no extra column: last cell and its fraction
             const int lg = min(l, nS - 2);
             const float *t0 = tabg + (int64_t)kk * nS + lg;
-            bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, k.c4, ai,
-                                        aj, phi, dqi, dqj);
+            bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, 1.0f, ei,
+                                        ej, phi, dqi, dqj);
         } else {
-            asymptote<float, ADJ, JSIDE>(k, m, ai, aj, phi, dqi, dqj);
+            asymptote<float, ADJ, JSIDE>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
         }
     }
 }
@@ -653,16 +663,24 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
                                        R (&acc)[IPL], R (&accq)[IPL], R &accj, R &accqj)
 {
     constexpr bool NORM = GEO == kCubic && sizeof(R) == 4;
-    R mx[IPL], my[IPL], mz[IPL], wi[IPL], ca[IPL], cq[IPL];
+    R mz[IPL], wi[IPL], ca[IPL], cq[IPL];
+    half2v mxy[IPL];
 #pragma unroll
     for (int p = 0; p < IPL; ++p) {
-        mx[p] = -2 * sx[p];
-        my[p] = -2 * sy[p];
+        if (NORM) mxy[p] = half2v{(_Float16)(float)(-2 * sx[p]), (_Float16)(float)(-2 * sy[p])};
         mz[p] = -2 * sz[p];
         wi[p] = sx[p] * sx[p] + sy[p] * sy[p] + sz[p] * sz[p];
         ca[p] = 0;  // Kahan terms (KAHAN only)
         cq[p] = 0;
     }
+    // NORM: the x, y coordinates of the j records as one f16 pair
+    half2v xyj = NORM ? half2v{(_Float16)(float)xj, (_Float16)(float)yj} : half2v{};
+    // FP32: the j point travels as ej = 4 csig a_j, the i points also carry ei
+    constexpr bool F32 = sizeof(R) == 4;
+    R ei[IPL];
+#pragma unroll
+    for (int p = 0; p < IPL; ++p) ei[p] = F32 ? kc.c4 * ai[p] : (R)0;
+    if (F32) aj = kc.c4 * aj;
     R cj = 0, cqj = 0;
     for (int st = 0; st < 64; ++st) {
         const R cj_ = cj_of(kc, aj);
@@ -671,12 +689,11 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
         for (int p = 0; p < IPL; ++p) {
             R m;
             if (NORM)
-                m = (R)dist2n((float)mx[p], (float)my[p], (float)mz[p], (float)(wi[p] + wj), (float)xj, (float)yj,
-                              (float)zj);
+                m = (R)__builtin_amdgcn_fdot2(mxy[p], xyj, fmaf((float)mz[p], (float)zj, (float)(wi[p] + wj)), false);
             else
                 m = dist2<R, GEO>(kc, sx[p] - xj, sy[p] - yj, sz[p] - zj);
             R ph, q = 0, jq = 0;
-            pair_eval<ADJ, true, NSIG>(kc, tab, tabg, m, ai[p], ci[p], aj, cj_, ph, q, jq);
+            pair_eval<ADJ, true, NSIG>(kc, tab, tabg, m, ai[p], ci[p], aj, F32 ? ei[p] : cj_, ph, q, jq);
             R wjp = nj, wip = ni[p];
             if (MASK) {
                 wjp = (m <= rcm) ? nj : (R)0;
@@ -702,8 +719,12 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
             kadd(accj, cj, sj);
             if (ADJ) kadd(accqj, cqj, sqj);
         }
-        xj = wrot(xj);
-        yj = wrot(yj);
+        if (NORM) {
+            xyj = wrot(xyj);
+        } else {
+            xj = wrot(xj);
+            yj = wrot(yj);
+        }
         zj = wrot(zj);
         if (NORM) wj = wrot(wj);
         aj = wrot(aj);
@@ -828,6 +849,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
     kc.tSclamp = (R)A.tSclamp;
     kc.csig = (R)A.csig;
     kc.c4 = (R)(4.0 * A.csig);
+    kc.rc4 = (R)(0.25 / A.csig);
     kc.casym = (R)A.casym;
     kc.S = A.S;
     kc.nS = nS;
@@ -935,6 +957,8 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                     for (int j = jr; j < je; ++j) {
                         const Rec J = Jn;
                         Jn = P[min(j + 1, j1 - 1)];  // prefetch the next record (wave-uniform)
+                        // FP32: the j point as ej = 4 csig a_j (see pair_eval)
+                        const R ajx = sizeof(R) == 4 ? kc.c4 * J.a : J.a;
                         const R cj = cj_of(kc, J.a);
 #pragma unroll
                         for (int p = 0; p < IPL; ++p) {
@@ -947,7 +971,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                             R wt = (m > (R)0) ? J.n : (R)0;
                             if (IMG) wt = (m <= rcm) ? wt : (R)0;
                             R ph, q = 0, unused;
-                            pair_eval<ADJ, false, NSIG>(kc, tab, tabg, m, ai[p], ci[p], J.a, cj, ph, q, unused);
+                            pair_eval<ADJ, false, NSIG>(kc, tab, tabg, m, ai[p], ci[p], ajx, cj, ph, q, unused);
                             if (KAHAN) {
                                 R y = wt * ph - cm[p], t = acc[p] + y;
                                 cm[p] = (t - acc[p]) - y;
@@ -1907,7 +1931,9 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
         const int n3[3] = {g.nx, g.ny, g.nz};
         for (int a = 0; a < 3; ++a) cmax = fmax(cmax, (double)n3[a] * (1 + P.mimg[a]));
     }
-    if (12.0 * cmax * cmax >= 16777216.0) E->geo = kOrtho;
+    // (and the ring takes -2x of the i-points and x of the j records as f16,
+    // exact while |2x| <= 2048)
+    if (12.0 * cmax * cmax >= 16777216.0 || cmax > 1024.0) E->geo = kOrtho;
     if (P.skew) E->geo = kSkew;
     PairPtrs none{};
     return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->geo, E->tpb, pa, none, E->grid, E->lds, nullptr,
