@@ -419,8 +419,10 @@ struct PairK {
 };
 
 // Grid geometry of a pair-kernel variant: orthorhombic, cubic (equal
-// spacings), or skew (general metric).
-constexpr int kOrtho = 0, kCubic = 1, kSkew = 2;
+// spacings), skew (general metric), or square (orthorhombic with h_x = h_y,
+// the slab's layout: x, y enter the squared distance exactly, as on cubic
+// grids, and z through its weight).
+constexpr int kOrtho = 0, kCubic = 1, kSkew = 2, kSquare = 3;
 
 // The NSIG template value of the FP64 kernels that read the table cubic in D
 // (any n_sigma); NSIG = 0: any n_sigma, bilinear; NSIG > 0: that n_sigma.
@@ -542,7 +544,7 @@ __device__ __forceinline__ double cubic_d(const PairK<double> &k, const double *
 }
 
 // FP64 form: ci = b_i = csig a_i and cj = csig a_j, u = (b_i - csig a_j) / s.
-template <bool ADJ, bool JSIDE, int NSIG>
+template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT>
 __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *tab, const double *__restrict__ tabg,
                                           double m, double ai, double ci, double aj, double cj, double &phi,
                                           double &dqi, double &dqj)
@@ -598,7 +600,7 @@ __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *
 // The LDS rows are read and interpolated for every pair; one compare
 // (t_D >= K - 1) sends the pairs beyond them to a second pass with the
 // global table or the asymptote, which few pairs take.
-template <bool ADJ, bool JSIDE, int NSIG>
+template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT>
 __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *tab, const float *__restrict__ tabg,
                                           float m, float ai, float ci, float ej, float ei, float &phi, float &dqi,
                                           float &dqj)
@@ -617,19 +619,38 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
     const int kk = (int)tD;
     const int l = (int)ts;
     const float fD = dfract(tD), fS = dfract(ts);
-    // the clamped LDS read is always in bounds
-    const int kl = min(kk, k.K - 2);
-    const float *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
-    bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
-    if (tD >= k.tDlds) {
-        if (tD < k.tDmax) {
+    // SPLIT (the image kernels, where many pairs lie beyond the LDS rows):
+    // each lane reads one table source, the LDS rows (t_D < K - 1, so the
+    // cell's rows kk and kk + 1 are both there), the global rows, or the
+    // asymptote, and a wavefront runs only the sources its lanes need
+    if (SPLIT) {
+        if (tD < k.tDlds) {
+            const float *t = tab + (__umul24((unsigned)kk, (unsigned)S) + (unsigned)l);
+            bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
+        } else if (tD < k.tDmax) {
             // global rows have no extra column: last cell and its fraction
             const int lg = min(l, nS - 2);
-            const float *t0 = tabg + (int64_t)kk * nS + lg;
+            const float *t0 = tabg + (uint32_t)(kk * nS + lg);
             bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, 1.0f, ei,
                                         ej, phi, dqi, dqj);
         } else {
             asymptote<float, ADJ, JSIDE>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
+        }
+    } else {
+        // every lane reads the LDS copy (the clamped read is in bounds); the
+        // pairs beyond it are redone from the global rows or the asymptote
+        const int kl = min(kk, k.K - 2);
+        const float *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
+        bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
+        if (tD >= k.tDlds) {
+            if (tD < k.tDmax) {
+                const int lg = min(l, nS - 2);
+                const float *t0 = tabg + (uint32_t)(kk * nS + lg);
+                bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, 1.0f,
+                                            ei, ej, phi, dqi, dqj);
+            } else {
+                asymptote<float, ADJ, JSIDE>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
+            }
         }
     }
 }
@@ -656,25 +677,30 @@ __device__ __forceinline__ void kadd(R &sum, R &c, R y)
 // pair by pair (only for tiles that straddle it).  NORM (FP32 on cubic
 // grids) takes the squared distance from the exact integer form of dist2n,
 // with |x_j|^2 rotating along.
-template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, int GEO, int IPL>
+template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, int GEO, int IPL, bool SPLIT>
 __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm,
                                        const R (&sx)[IPL], const R (&sy)[IPL], const R (&sz)[IPL], const R (&ai)[IPL],
                                        const R (&ci)[IPL], const R (&ni)[IPL], R xj, R yj, R zj, R wj, R aj, R nj,
                                        R (&acc)[IPL], R (&accq)[IPL], R &accj, R &accqj)
 {
     constexpr bool NORM = GEO == kCubic && sizeof(R) == 4;
+    // square grids: x, y exactly as NORM (|x_i|^2 + |x_j|^2 - 2 x_i . x_j over
+    // x and y), then the z term w_z (z_i - z_j)^2
+    constexpr bool SQXY = GEO == kSquare && sizeof(R) == 4;
     R mz[IPL], wi[IPL], ca[IPL], cq[IPL];
     half2v mxy[IPL];
 #pragma unroll
     for (int p = 0; p < IPL; ++p) {
-        if (NORM) mxy[p] = half2v{(_Float16)(float)(-2 * sx[p]), (_Float16)(float)(-2 * sy[p])};
+        if (NORM || SQXY) mxy[p] = half2v{(_Float16)(float)(-2 * sx[p]), (_Float16)(float)(-2 * sy[p])};
         mz[p] = -2 * sz[p];
-        wi[p] = sx[p] * sx[p] + sy[p] * sy[p] + sz[p] * sz[p];
+        wi[p] = SQXY ? sx[p] * sx[p] + sy[p] * sy[p] : sx[p] * sx[p] + sy[p] * sy[p] + sz[p] * sz[p];
         ca[p] = 0;  // Kahan terms (KAHAN only)
         cq[p] = 0;
     }
-    // NORM: the x, y coordinates of the j records as one f16 pair
-    half2v xyj = NORM ? half2v{(_Float16)(float)xj, (_Float16)(float)yj} : half2v{};
+    // NORM, SQXY: the x, y coordinates of the j records as one f16 pair; SQXY
+    // carries x_j^2 + y_j^2 in wj
+    half2v xyj = (NORM || SQXY) ? half2v{(_Float16)(float)xj, (_Float16)(float)yj} : half2v{};
+    if (SQXY) wj = xj * xj + yj * yj;
     // FP32: the j point travels as ej = 4 csig a_j, the i points also carry ei
     constexpr bool F32 = sizeof(R) == 4;
     R ei[IPL];
@@ -690,10 +716,13 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
             R m;
             if (NORM)
                 m = (R)__builtin_amdgcn_fdot2(mxy[p], xyj, fmaf((float)mz[p], (float)zj, (float)(wi[p] + wj)), false);
-            else
+            else if (SQXY) {
+                const float dz = (float)sz[p] - (float)zj;
+                m = (R)fmaf((float)kc.wz * dz, dz, __builtin_amdgcn_fdot2(mxy[p], xyj, (float)(wi[p] + wj), false));
+            } else
                 m = dist2<R, GEO>(kc, sx[p] - xj, sy[p] - yj, sz[p] - zj);
             R ph, q = 0, jq = 0;
-            pair_eval<ADJ, true, NSIG>(kc, tab, tabg, m, ai[p], ci[p], aj, F32 ? ei[p] : cj_, ph, q, jq);
+            pair_eval<ADJ, true, NSIG, SPLIT>(kc, tab, tabg, m, ai[p], ci[p], aj, F32 ? ei[p] : cj_, ph, q, jq);
             R wjp = nj, wip = ni[p];
             if (MASK) {
                 wjp = (m <= rcm) ? nj : (R)0;
@@ -719,14 +748,14 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
             kadd(accj, cj, sj);
             if (ADJ) kadd(accqj, cqj, sqj);
         }
-        if (NORM) {
+        if (NORM || SQXY) {
             xyj = wrot(xyj);
         } else {
             xj = wrot(xj);
             yj = wrot(yj);
         }
         zj = wrot(zj);
-        if (NORM) wj = wrot(wj);
+        if (NORM || SQXY) wj = wrot(wj);
         aj = wrot(aj);
         nj = wrot(nj);
         accj = wrot(accj);
@@ -971,7 +1000,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                             R wt = (m > (R)0) ? J.n : (R)0;
                             if (IMG) wt = (m <= rcm) ? wt : (R)0;
                             R ph, q = 0, unused;
-                            pair_eval<ADJ, false, NSIG>(kc, tab, tabg, m, ai[p], ci[p], ajx, cj, ph, q, unused);
+                            pair_eval<ADJ, false, NSIG, IMG>(kc, tab, tabg, m, ai[p], ci[p], ajx, cj, ph, q, unused);
                             if (KAHAN) {
                                 R y = wt * ph - cm[p], t = acc[p] + y;
                                 cm[p] = (t - acc[p]) - y;
@@ -1062,11 +1091,11 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                     R accj = 0, accqj = 0;
                     const R nj0 = jv ? Jr.n : (R)0;
                     if (masked)
-                        ring64<R, ADJ, true, KAHAN, NSIG, GEO, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
+                        ring64<R, ADJ, true, KAHAN, NSIG, GEO, IPL, IMG>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
                                                                       Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
                                                                       accqj);
                     else
-                        ring64<R, ADJ, false, KAHAN, NSIG, GEO, IPL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
+                        ring64<R, ADJ, false, KAHAN, NSIG, GEO, IPL, IMG>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
                                                                        Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
                                                                        accqj);
 #pragma unroll
@@ -1815,8 +1844,9 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
                     : launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (kahan) return launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (nsig == 64)
-        return geo == kCubic ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
-                             : launch_pair_v<float, false, 64, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        return geo == kCubic    ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+               : geo == kSquare ? launch_pair_v<float, false, 64, kSquare>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                                : launch_pair_v<float, false, 64, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     return launch_pair_v<float, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
 }
 
@@ -1924,16 +1954,24 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     // shifts included), exact in FP32 while 12 c_max^2 < 2^24; skew cells
     // take the general metric
     E->geo = kCubic;
-    double cmax = 0.0;
+    bool square = true;
+    double cmax = 0.0, cxy = 0.0;
     for (int b = 0; b < B; ++b) {
         const Seg &g = P.segs[b];
         if (!(g.hx == g.hy && g.hx == g.hz)) E->geo = kOrtho;
+        if (!(g.hx == g.hy)) square = false;
         const int n3[3] = {g.nx, g.ny, g.nz};
         for (int a = 0; a < 3; ++a) cmax = fmax(cmax, (double)n3[a] * (1 + P.mimg[a]));
+        for (int a = 0; a < 2; ++a) cxy = fmax(cxy, (double)n3[a] * (1 + P.mimg[a]));
     }
     // (and the ring takes -2x of the i-points and x of the j records as f16,
     // exact while |2x| <= 2048)
     if (12.0 * cmax * cmax >= 16777216.0 || cmax > 1024.0) E->geo = kOrtho;
+    // square grids (h_x = h_y): the x, y part exactly in the same way, its
+    // partial sums below 8 c^2 (FP32 n_sigma = 64 kernels without Kahan runs)
+    if (E->geo == kOrtho && square && !E->fp64 && !E->kahan && E->nsig == 64 && 8.0 * cxy * cxy < 16777216.0 &&
+        cxy <= 1024.0)
+        E->geo = kSquare;
     if (P.skew) E->geo = kSkew;
     PairPtrs none{};
     return launch_pair(E->fp64, adj, P.img ? 1 : 0, E->kahan, E->nsig, E->geo, E->tpb, pa, none, E->grid, E->lds, nullptr,
