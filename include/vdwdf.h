@@ -48,7 +48,7 @@ enum {
     VDW_EINVAL = -1,        /* bad argument: null pointer, size, parameter range  */
     VDW_ENOMEM = -2,        /* host allocation failed (batch plan object)         */
     VDW_EHIP = -3,          /* a HIP runtime call failed                          */
-    VDW_EUNSUPPORTED = -4,  /* valid but not offered (e.g. the cubic-in-D table in FP32C) */
+    VDW_EUNSUPPORTED = -4,  /* valid but not offered (e.g. the cubic-in-D table with Kahan runs) */
     VDW_EWORKSPACE = -5,    /* workspace smaller than enl_workspace_size()        */
     VDW_ENONFINITE = -6     /* NaN or Inf found in the density                    */
 };
@@ -109,8 +109,8 @@ typedef struct {
                                bilinearly, or cubic in D (Catmull-Rom form of
                                each sigma column, rows beyond the ends
                                extrapolated linearly; C1 in D) and linear in
-                               sigma.  The cubic form is offered with
-                               VDW_FP64 (VDW_FP32C gives VDW_EUNSUPPORTED). */
+                               sigma, in either precision (not with Kahan
+                               runs: VDW_EUNSUPPORTED). */
 } vdw_table_params;
 
 enum { VDW_INTERP_BILINEAR = 0, VDW_INTERP_CUBIC_D = 1 };
@@ -277,7 +277,7 @@ size_t enl_workspace_size(const vdw_grid *grid, const vdw_table_params *tp, cons
  *   ws, ws_bytes: device workspace of at least enl_workspace_size() bytes.
  *   E_out:     host, 3 doubles: {E_pair0, E_pairL, E_self} (Hartree).
  * Errors: VDW_EINVAL, VDW_EUNSUPPORTED (the cubic-in-D table with
- * VDW_FP32C), VDW_EWORKSPACE, VDW_EHIP.
+ * Kahan runs), VDW_EWORKSPACE, VDW_EHIP.
  * ------------------------------------------------------------------- */
 int enl_energy(const vdw_grid *grid, const double *n_d, const double *q0_d, const double *phi_d,
                const float *phi_f, const vdw_table_params *tp, const vdw_opts *opts, void *ws,

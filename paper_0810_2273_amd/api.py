@@ -29,7 +29,7 @@ class TableParams:
     graded_levels: int = 12
     kappa: float = 16.0
     A0: float = 512.0
-    interp: int = 0  # 0 bilinear, 1 cubic (C1) in D and linear in sigma (FP64 form)
+    interp: int = 0  # 0 bilinear, 1 cubic (C1) in D and linear in sigma
 
     def c(self) -> L.VdwTableParams:
         return L.VdwTableParams(self.n_D, self.n_sigma, self.D_max, self.gl_points, self.graded_levels,

@@ -543,6 +543,46 @@ __device__ __forceinline__ double cubic_d(const PairK<double> &k, const double *
     return v0 + fS * (v1 - v0);
 }
 
+// FP32 form of cubic_d: the same rows (LDS when all four are held there,
+// else global, whose rows lack the extra column: there the last cell and its
+// fraction), the Catmull-Rom cubic per column, linear in sigma.
+__device__ __forceinline__ float catmull_rom(const float (&f)[4], float t, float &dt)
+{
+    const float m1 = 0.5f * (f[2] - f[0]), m2 = 0.5f * (f[3] - f[1]);
+    const float t2 = t * t, t3 = t2 * t;
+    dt = (6.0f * t2 - 6.0f * t) * (f[1] - f[2]) + (3.0f * t2 - 4.0f * t + 1.0f) * m1 + (3.0f * t2 - 2.0f * t) * m2;
+    return (2.0f * t3 - 3.0f * t2 + 1.0f) * f[1] + (t3 - 2.0f * t2 + t) * m1 + (-2.0f * t3 + 3.0f * t2) * f[2] +
+           (t3 - t2) * m2;
+}
+
+__device__ __forceinline__ float cubic_d32(const PairK<float> &k, const float *tab, const float *__restrict__ tabg,
+                                           int kk, int l, float fD, float ts, float &gD, float &gS)
+{
+    const bool lds = kk >= 1 && kk + 2 <= k.K - 1;
+    const int lg = lds ? l : min(l, k.nS - 2);
+    const float fS = ts - (float)lg;
+    float c0[4], c1[4];
+    for (int i = 0; i < 4; ++i) {
+        const int rr = min(max(kk - 1 + i, 0), k.nD - 1);
+        const float *t = lds ? tab + (int64_t)rr * k.S + lg : tabg + (int64_t)rr * k.nS + lg;
+        c0[i] = t[0];
+        c1[i] = t[1];
+    }
+    if (kk == 0) {
+        c0[0] = 2.0f * c0[1] - c0[2];
+        c1[0] = 2.0f * c1[1] - c1[2];
+    }
+    if (kk + 2 > k.nD - 1) {
+        c0[3] = 2.0f * c0[2] - c0[1];
+        c1[3] = 2.0f * c1[2] - c1[1];
+    }
+    float d0, d1;
+    const float v0 = catmull_rom(c0, fD, d0), v1 = catmull_rom(c1, fD, d1);
+    gD = d0 + fS * (d1 - d0);
+    gS = v1 - v0;
+    return v0 + fS * (v1 - v0);
+}
+
 // FP64 form: ci = b_i = csig a_i and cj = csig a_j, u = (b_i - csig a_j) / s.
 template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT>
 __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *tab, const double *__restrict__ tabg,
@@ -619,6 +659,21 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
     const int kk = (int)tD;
     const int l = (int)ts;
     const float fD = dfract(tD), fS = dfract(ts);
+    if constexpr (NSIG == kCubicD) {
+        if (tD < k.tDmax) {
+            float gD, gS;
+            phi = cubic_d32(k, tab, tabg, kk, l, fD, ts, gD, gS);
+            if (ADJ) {
+                const float X = gD * r;
+                const float Z = (gS * (u * inv)) * inv;
+                dqi = fmaf(Z, ej, X);
+                if (JSIDE) dqj = fmaf(-Z, ei, X);
+            }
+        } else {
+            asymptote<float, ADJ, JSIDE>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
+        }
+        return;
+    }
     // SPLIT (the image kernels, where many pairs lie beyond the LDS rows):
     // each lane reads one table source, the LDS rows (t_D < K - 1, so the
     // cell's rows kk and kk + 1 are both there), the global rows, or the
@@ -1521,6 +1576,11 @@ void voxel_rule(double *u, double *wt)
 // keep every CU busy to the end.
 constexpr int64_t kCUs = 256;
 
+// The n_sigma the work layout is planned for: the table's, except for the
+// cubic-in-D interpolant, whose kernels have two i-points per lane (the
+// layout of any n_sigma).
+int plan_nsig(const vdw_table_params *tp) { return tp->interp == VDW_INTERP_CUBIC_D ? kCubicD : tp->n_sigma; }
+
 int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int nsig, int fp64, int adj,
               Plan *P)
 {
@@ -1830,7 +1890,10 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
                 const PairPtrs &p, int grid, size_t lds, hipStream_t s, bool attr_only)
 {
     const bool cubd = a.interp == VDW_INTERP_CUBIC_D;
-    if (cubd && !fp64) return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is offered with VDW_FP64 only");
+    if (cubd && kahan) return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is not offered with Kahan runs");
+    if (cubd && !fp64)
+        return geo == kSkew ? launch_pair_v<float, false, kCubicD, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                            : launch_pair_v<float, false, kCubicD, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (geo == kSkew) {
         if (kahan) return launch_pair_v<float, true, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
         if (fp64)
@@ -1877,8 +1940,8 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     if (rc) return rc;
     rc = validate_table(tp);
     if (rc) return rc;
-    if (tp->interp == VDW_INTERP_CUBIC_D && o->precision != VDW_FP64)
-        return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is offered with VDW_FP64 only");
+    if (tp->interp == VDW_INTERP_CUBIC_D && o->kahan)
+        return fail(VDW_EUNSUPPORTED, "the cubic-in-D interpolant is not offered with Kahan runs");
     if (B < 1) return fail(VDW_EINVAL, "B must be >= 1");
     if (!grids) return fail(VDW_EINVAL, "NULL argument");
     if (!ws) return fail(VDW_EINVAL, "workspace is NULL");
@@ -1893,7 +1956,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     E->self_term = o->self_term;
     E->interp = tp->interp;
     E->n_cut = o->n_cut;
-    rc = make_plan(B, grids, grid_off, o, tp->n_sigma, E->fp64, adj, &E->P);
+    rc = make_plan(B, grids, grid_off, o, plan_nsig(tp), E->fp64, adj, &E->P);
     if (rc) return rc;
     const Plan &P = E->P;
     if (ws_bytes < P.L.total) return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
@@ -2316,7 +2379,7 @@ extern "C" size_t enl_batched_workspace_size(int32_t B, const vdw_grid *grids, c
 {
     if (B < 1 || !grids || validate_opts(opts) || validate_table(tp)) return 0;
     Plan P;
-    if (make_plan(B, grids, nullptr, opts, tp->n_sigma, opts->precision == VDW_FP64, 1, &P)) return 0;
+    if (make_plan(B, grids, nullptr, opts, plan_nsig(tp), opts->precision == VDW_FP64, 1, &P)) return 0;
     return P.L.total;
 }
 

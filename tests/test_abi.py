@@ -206,8 +206,8 @@ def test_spectral_gradient_host_validation(L):
 
 
 def test_cubic_interpolant_host_validation(L):
-    """interp must be 0 or 1, and the cubic form is refused for FP32C before
-    any device work."""
+    """interp must be 0 or 1, and the cubic form is refused for Kahan runs
+    before any device work."""
     lib = L.lib()
     dummy = ct.c_void_p(16)  # never dereferenced
     g = L.VdwGrid()
@@ -219,13 +219,14 @@ def test_cubic_interpolant_host_validation(L):
     o.self_term = 1
     o.table_lds_rows = -1
     o.precision = 1
+    o.kahan = 1
     E = (ct.c_double * 3)()
     tp = L.VdwTableParams(64, 16, 12.0, 8, 12, 4.0, 64.0, 2)
     assert lib.build_phi_table(ct.byref(tp), dummy, None, None) == L.VDW_EINVAL
     tp = L.VdwTableParams(64, 16, 12.0, 8, 12, 4.0, 64.0, 1)
     assert lib.enl_energy(ct.byref(g), dummy, dummy, dummy, dummy, ct.byref(tp), ct.byref(o), dummy, 1 << 30, E,
                           None) == L.VDW_EUNSUPPORTED
-    assert b"FP64" in lib.vdw_last_error()
+    assert b"Kahan" in lib.vdw_last_error()
 
 
 def test_far_shell_host_validation(L):

@@ -1,8 +1,9 @@
-"""GPU parity of the C1 table interpolant (interp = 1, cubic in D; FP64
-form) against the oracle, element by element (energies 1e-12, dE/dn 1e-10
-in the L2 norm): open and periodic grids with images and a cut, a skew
-cell, the small-grid 256-thread shape, rows read from the global table
-(LDS rows cut to a few), both on-site forms; FP32C refuses it."""
+"""GPU parity of the C1 table interpolant (interp = 1, cubic in D) against
+the oracle, element by element: FP64 form energies 1e-12 and dE/dn 1e-10 in
+the L2 norm, FP32C form 1e-6 and 1e-4; open and periodic grids with images
+and a cut, a skew cell, the small-grid 256-thread shape, rows read from the
+global table (LDS rows cut to a few), both on-site forms.  Kahan runs
+refuse it."""
 import numpy as np
 import pytest
 
@@ -64,21 +65,22 @@ def test_cubic_interpolant(V, oracle, tt, c):
                            graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0, interp=1)
     t64 = torch.tensor(tab, dtype=torch.float64, device="cuda:0").contiguous()
     table = V.Table(params, t64, t64.float().contiguous())
-    opts = V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=0, **extra)
-    E, v = V.enl_potential(g, n, qd, table, opts)
-    v = v.cpu().numpy()
-    st = V.last_stats()
-    rel_e = abs(sum(E) - ref.E) / abs(ref.E)
-    rel_v = np.linalg.norm(v - ref.dEdn) / np.linalg.norm(ref.dEdn)
-    say(f"cubic case {c}: N={st['retained']} threads={st['block_threads']} lds_rows={st['lds_rows']} "
-        f"dE={rel_e:.1e} dv={rel_v:.1e}")
-    assert rel_e <= 1e-12
-    for a, b in ((E[0], ref.E_pair0), (E[1], ref.E_pairL), (E[2], ref.E_self)):
-        assert abs(a - b) <= 1e-12 * abs(ref.E) + 1e-300
-    assert rel_v <= 1e-10
+    for prec, etol, vtol in ((0, 1e-12, 1e-10), (1, 1e-6, 1e-4)):
+        opts = V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec, **extra)
+        E, v = V.enl_potential(g, n, qd, table, opts)
+        v = v.cpu().numpy()
+        st = V.last_stats()
+        rel_e = abs(sum(E) - ref.E) / abs(ref.E)
+        rel_v = np.linalg.norm(v - ref.dEdn) / np.linalg.norm(ref.dEdn)
+        say(f"cubic case {c} precision={prec}: N={st['retained']} threads={st['block_threads']} "
+            f"lds_rows={st['lds_rows']} dE={rel_e:.1e} dv={rel_v:.1e}")
+        assert rel_e <= etol
+        for a, b in ((E[0], ref.E_pair0), (E[1], ref.E_pairL), (E[2], ref.E_self)):
+            assert abs(a - b) <= etol * abs(ref.E) + 1e-300
+        assert rel_v <= vtol
     # the bilinear table gives a different energy
     bil = oracle.table_params(n_D=256, n_sigma=16, D_max=16.0, **CHEAP_RULE)
     assert abs(oracle.evaluate(og, wl.rho, tab, bil, wl.n_cut, wl.image_max, wl.r_cut, self_term=st_term).E - ref.E) \
         > 1e-9 * abs(ref.E)
     with pytest.raises(V.VdwError):
-        V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, precision=1))
+        V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, precision=1, kahan=1))
