@@ -263,14 +263,68 @@ def self_voxel_many(q, steps, tab, tp, g=VOXEL_GL_POINTS):
     return phi, dphi
 
 
+# Phi_V(q) tabulated over ln q (the on-site term self_term = 2): nodes
+# ln q_k = VOXEL_LNQ_LO + k * dlnq, k = 0 .. VOXEL_TABLE_NODES - 1, spanning
+# q in [2^-6, 2^7], each node by the voxel rule; between nodes the Catmull-Rom
+# cubic in ln q (rows beyond the ends extrapolated linearly); q outside the
+# range takes the rule directly.
+VOXEL_TABLE_NODES = 4096
+VOXEL_LNQ_LO = -6.0 * math.log(2.0)
+VOXEL_LNQ_HI = 7.0 * math.log(2.0)
+
+
+_VOXEL_TABLES = {}
+
+
+def voxel_table(steps, tab, tp):
+    """Phi_V at the ln q nodes, for the grid cell spanned by `steps` (kept
+    for the last few (cell, table) pairs)."""
+    tab = np.ascontiguousarray(tab, dtype=np.float64)
+    key = (tuple(np.asarray(steps, dtype=np.float64).ravel()), tab.shape, hash(tab.tobytes()),
+           tuple(getattr(tp, f) for f, _ in tp._fields_))
+    if key not in _VOXEL_TABLES:
+        if len(_VOXEL_TABLES) >= 4:
+            _VOXEL_TABLES.pop(next(iter(_VOXEL_TABLES)))
+        x = VOXEL_LNQ_LO + np.arange(VOXEL_TABLE_NODES) * ((VOXEL_LNQ_HI - VOXEL_LNQ_LO) / (VOXEL_TABLE_NODES - 1))
+        _VOXEL_TABLES[key] = self_voxel_many(np.exp(x), steps, tab, tp)[0]
+    return _VOXEL_TABLES[key]
+
+
+def voxel_interp(vt, q, steps, tab, tp):
+    """(Phi_V, dPhi_V/dq) at the array q from the node values vt: the
+    Catmull-Rom cubic in ln q, its derivative divided by q; outside the
+    node range the voxel rule itself."""
+    q = np.atleast_1d(np.asarray(q, dtype=np.float64))
+    n = len(vt)
+    dx = (VOXEL_LNQ_HI - VOXEL_LNQ_LO) / (n - 1)
+    f = np.concatenate([[2 * vt[0] - vt[1]], vt, [2 * vt[-1] - vt[-2]]])  # f[k + 1] = node k
+    phi = np.zeros(len(q))
+    dphi = np.zeros(len(q))
+    inside = (q >= math.exp(VOXEL_LNQ_LO)) & (q <= math.exp(VOXEL_LNQ_HI))
+    xs = (np.log(q[inside]) - VOXEL_LNQ_LO) / dx
+    k = np.clip(np.floor(xs).astype(np.int64), 0, n - 2)
+    t = xs - k
+    f0, f1, f2, f3 = f[k], f[k + 1], f[k + 2], f[k + 3]
+    m1, m2 = 0.5 * (f2 - f0), 0.5 * (f3 - f1)
+    t2, t3 = t * t, t * t * t
+    phi[inside] = (2 * t3 - 3 * t2 + 1) * f1 + (t3 - 2 * t2 + t) * m1 + (-2 * t3 + 3 * t2) * f2 + (t3 - t2) * m2
+    dt = (6 * t2 - 6 * t) * (f1 - f2) + (3 * t2 - 4 * t + 1) * m1 + (3 * t2 - 2 * t) * m2
+    dphi[inside] = dt / (dx * q[inside])
+    if (~inside).any():
+        phi[~inside], dphi[~inside] = self_voxel_many(q[~inside], steps, tab, tp)
+    return phi, dphi
+
+
 def onsite_phi(grid, q, tab, tp, self_term):
     """The on-site value and its q-derivative: self_term 1 (or True) takes
     phi~(q rho_s, 0) with the sphere radius of self_radius, 2 the voxel
-    double average, 0 (or False) nothing."""
+    double average through its table over ln q, 0 (or False) nothing."""
     if self_term is True or self_term == 1:
         return self_phi(q, self_radius(grid.dV), tab, tp)
     if self_term == 2:
-        return self_voxel(q, grid.steps, tab, tp)
+        vt = voxel_table(grid.steps, tab, tp)
+        p, d = voxel_interp(vt, [q], grid.steps, tab, tp)
+        return float(p[0]), float(d[0])
     return 0.0, 0.0
 
 
@@ -783,7 +837,7 @@ def evaluate(grid: Grid, rho, tab, tp, n_cut, image_max=(0, 0, 0), r_cut=0.0, se
     Phi = np.zeros(len(nS))
     dPhi = np.zeros(len(nS))
     if self_term == 2:
-        Phi, dPhi = self_voxel_many(qS, grid.steps, tab, tp)
+        Phi, dPhi = voxel_interp(voxel_table(grid.steps, tab, tp), qS, grid.steps, tab, tp)
     elif self_term:
         for t in range(len(nS)):
             Phi[t], dPhi[t] = onsite_phi(grid, qS[t], tab, tp, self_term)

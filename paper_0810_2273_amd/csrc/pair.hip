@@ -1196,6 +1196,10 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
 // ---------------------------------------------------------------------------
 
 constexpr int kVoxelGL = 8;  // Gauss-Legendre points per octant axis of the voxel on-site rule
+// The voxel on-site term is read from a table of Phi_V over ln q: kVoxNodes
+// nodes from ln 2^-6 to ln 2^7 (q outside takes the rule directly).
+constexpr int kVoxNodes = 4096;
+constexpr double kVoxLnLo = -6.0 * 0.69314718055994530942, kVoxLnHi = 7.0 * 0.69314718055994530942;
 
 struct FinArgs {
     const Seg *segs;
@@ -1216,6 +1220,7 @@ struct FinArgs {
     int nD, nS;
     double dD, Dmax, casym;
     double *blockE;
+    const double *vox;  // self_term = 2: Phi_V at the ln q nodes, kVoxNodes per density
     unsigned long long *qmin;  // per density: bits of the smallest q0 of a kept point (positive doubles order as integers)
     double *dEdn;   // direct part scattered to the grid (potential)
     double *dEdq;   // dE/dq scattered to the grid (potential)
@@ -1279,6 +1284,35 @@ __device__ inline double voxel_phi(const FinArgs &F, const double *e, double q, 
     return acc;
 }
 
+// Phi_V at the ln q nodes of every density: one thread per node.
+__global__ __launch_bounds__(256) void voxel_table_kernel(FinArgs F, double *__restrict__ vox)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x, b = blockIdx.y;
+    if (k >= kVoxNodes) return;
+    const double x = kVoxLnLo + k * ((kVoxLnHi - kVoxLnLo) / (kVoxNodes - 1));
+    double d;
+    vox[(int64_t)b * kVoxNodes + k] = voxel_phi(F, F.segs[b].e, exp(x), &d);
+}
+
+// Phi_V(q) and dPhi_V/dq from the node values of one density: the
+// Catmull-Rom cubic in ln q (rows beyond the ends extrapolated linearly).
+__device__ inline double voxel_interp(const double *__restrict__ vt, double q, double *dPhi)
+{
+    const double dx = (kVoxLnHi - kVoxLnLo) / (kVoxNodes - 1);
+    const double xs = (log(q) - kVoxLnLo) / dx;
+    const int k = min(max((int)floor(xs), 0), kVoxNodes - 2);
+    const double t = xs - k;
+    double f[4];
+    f[1] = vt[k];
+    f[2] = vt[k + 1];
+    f[0] = k > 0 ? vt[k - 1] : 2.0 * f[1] - f[2];
+    f[3] = k + 2 < kVoxNodes ? vt[k + 2] : 2.0 * f[2] - f[1];
+    double dt;
+    const double v = catmull_rom(f, t, dt);
+    *dPhi = dt / (dx * q);
+    return v;
+}
+
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
 {
     __shared__ double r0[kFinThreads], r1[kFinThreads], r2[kFinThreads];
@@ -1325,7 +1359,10 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(FinArgs F)
         const double rho_s = cbrt(3.0 * sg.dV / (4.0 * 3.14159265358979323846)) * exp(-1.0 / 3.0);
         double Phi = 0.0, dPhi = 0.0;
         if (F.self_term == 2) {
-            Phi = voxel_phi(F, sg.e, q, &dPhi);
+            if (q >= exp(kVoxLnLo) && q <= exp(kVoxLnHi))
+                Phi = voxel_interp(F.vox + (int64_t)b * kVoxNodes, q, &dPhi);
+            else
+                Phi = voxel_phi(F, sg.e, q, &dPhi);
         } else if (F.self_term) {
             double dphi_dD;
             Phi = self_phi(F, q * rho_s, &dphi_dD);
@@ -1502,8 +1539,8 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, qmin, dEdq, fartab,
-        far, total;
+    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, qmin, vox, dEdq,
+        fartab, far, total;
     int64_t nblocks, slots, rows, fin_blocks, Gtot;
 };
 
@@ -1797,6 +1834,8 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     off = align256(off + (4 * B + 1) * sizeof(double));
     L.qmin = off;
     off = align256(off + B * sizeof(uint64_t));
+    L.vox = off;
+    if (o->self_term == 2) off = align256(off + (size_t)B * kVoxNodes * sizeof(double));
     L.dEdq = off;
     if (adj) off = align256(off + Gtot * sizeof(double));
     L.fartab = off;
@@ -2177,6 +2216,12 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
     fa.qmin = qmin;
     fa.dEdn = dEdn_d;
     fa.dEdq = dEdq;
+    fa.vox = (const double *)(w + L.vox);
+    if (E.self_term == 2) {
+        hipLaunchKernelGGL(voxel_table_kernel, dim3((kVoxNodes + 255) / 256, B), dim3(256), 0, s, fa,
+                           (double *)(w + L.vox));
+        VDW_HIP(hipGetLastError());
+    }
     if (L.fin_blocks > 0)
         hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)L.fin_blocks), dim3(kFinThreads), 0, s, fa);
     hipLaunchKernelGGL(seg_reduce_kernel, dim3(B), dim3(256), 0, s, (const Seg *)segs, (const double *)blockE, res, B,

@@ -1,8 +1,8 @@
 """GPU parity of the voxel on-site term (self_term = 2) against the oracle:
 energies and dE/dn element by element (FP64: 1e-12 / 1e-10, FP32C: 1e-6 /
 1e-4) on an orthorhombic and a skew grid, and E_self of the 96^3 Kr dimer
-in the bench launch configuration against the oracle's rule at sampled
-points (the term is per point)."""
+in the bench launch configuration against the oracle's term (its table of
+Phi_V over ln q, interpolated) over every kept point."""
 import numpy as np
 import pytest
 
@@ -75,7 +75,7 @@ def test_voxel_term_energy_and_potential(V, oracle, tt, skew):
 
 def test_voxel_term_full_size(V, oracle):
     """96^3 Kr dimer (576 596 kept points): E_self of the voxel term from the
-    GPU against the oracle's rule over every kept point (q0 from the oracle,
+    GPU against the oracle's tabulated term over every kept point (q0 from the oracle,
     equal to the GPU's to rounding); the pair energies do not change."""
     import time
 
@@ -99,7 +99,7 @@ def test_voxel_term_full_size(V, oracle):
     r = wl.rho.reshape(-1)
     q = oracle.compute_q0(og, r, wl.n_cut)["q0"]
     keep = np.flatnonzero(r >= wl.n_cut)
-    phi, _ = oracle.self_voxel_many(q[keep], og.steps, tab, tp)
+    phi, _ = oracle.voxel_interp(oracle.voxel_table(og.steps, tab, tp), q[keep], og.steps, tab, tp)
     ref = 0.5 * og.dV ** 2 * float(np.sum(r[keep] ** 2 * phi))
     say(f"  oracle E_self (voxel) {ref:.10e}")
     assert E2[2] == pytest.approx(ref, rel=1e-11)

@@ -89,3 +89,33 @@ def test_adjoint_with_voxel_term(oracle):
         eps = 2e-5 * rho[k]
         fd = oracle.local_energy_change(g, rho, k, eps, tab, tp, wl.n_cut, wl.image_max, 0.0, self_term=2) / (2 * eps)
         assert fd == pytest.approx(res.dEdn[k], rel=1e-5, abs=1e-10 * np.abs(res.dEdn).max()), k
+
+
+def test_voxel_table_against_the_rule(oracle, table_cache):
+    """self_term = 2 reads Phi_V from its table over ln q (4096 nodes on
+    q in [2^-6, 2^7]): the node values are the rule's, between nodes the
+    Catmull-Rom cubic in ln q stays within 1e-5 of the largest |Phi_V| of the
+    rule (the rule itself is good to ~1e-4, its kinks from the kernel table's
+    bilinear form limiting the cubic's accuracy), q outside the range takes
+    the rule itself, and dPhi_V/dq is the interpolant's own derivative."""
+    tp, tab = table_cache(n_D=256, n_sigma=16, D_max=12.0, gl_points=6, graded_levels=8, kappa=2.0, A0=20.0)
+    E = np.diag([0.25, 0.3, 0.35])
+    vt = oracle.voxel_table(E, tab, tp)
+    n = oracle.VOXEL_TABLE_NODES
+    assert len(vt) == n
+    xk = oracle.VOXEL_LNQ_LO + np.array([0, 1, 777, n - 2, n - 1]) * (
+        (oracle.VOXEL_LNQ_HI - oracle.VOXEL_LNQ_LO) / (n - 1))
+    qk = np.exp(xk)
+    direct = oracle.self_voxel_many(qk, E, tab, tp)[0]
+    assert np.allclose(oracle.voxel_interp(vt, qk, E, tab, tp)[0], direct, rtol=1e-12, atol=0)
+    rng = np.random.default_rng(5)
+    q = np.exp(rng.uniform(oracle.VOXEL_LNQ_LO, oracle.VOXEL_LNQ_HI, 200))
+    got, dgot = oracle.voxel_interp(vt, q, E, tab, tp)
+    ref = oracle.self_voxel_many(q, E, tab, tp)[0]
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    eps = 1e-7 * q
+    fp = oracle.voxel_interp(vt, q + eps, E, tab, tp)[0]
+    fm = oracle.voxel_interp(vt, q - eps, E, tab, tp)[0]
+    assert np.allclose((fp - fm) / (2 * eps), dgot, rtol=1e-5, atol=1e-9 * np.abs(dgot).max())
+    out = np.array([1e-3, 300.0])
+    assert np.array_equal(oracle.voxel_interp(vt, out, E, tab, tp)[0], oracle.self_voxel_many(out, E, tab, tp)[0])
