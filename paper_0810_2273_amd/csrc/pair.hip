@@ -128,6 +128,17 @@ __global__ void max_words_kernel(unsigned long long *__restrict__ a, int n)
     if (t < n) a[t] = ~0ull;
 }
 
+// The FP32 table's cells as corner quadruples (k, l), (k, l+1), (k+1, l),
+// (k+1, l+1), cell k (nS - 1) + l: one 16-byte load per pair beyond the LDS rows.
+__global__ void quad_kernel(const float *__restrict__ t, float4 *__restrict__ quad, int nD, int nS)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)(nD - 1) * (nS - 1)) return;
+    const int k = (int)(c / (nS - 1)), l = (int)(c - (int64_t)k * (nS - 1));
+    const float *r = t + (int64_t)k * nS + l;
+    quad[c] = make_float4(r[0], r[1], r[nS], r[nS + 1]);
+}
+
 // Brick-order position -> grid coordinates of one segment; false if outside.
 __device__ inline bool brick_pos(const Seg &s, int64_t lt, int &x, int &y, int &z)
 {
@@ -416,6 +427,9 @@ struct PairK {
     R en[9];
     int S, nS, K;
     int nD;           // table rows
+    // FP32 image kernels: the global table as one float4 per cell, the
+    // corners (k, l), (k, l+1), (k+1, l), (k+1, l+1) of cell k (n_sigma - 1) + l
+    const float4 *quad;
 };
 
 // Grid geometry of a pair-kernel variant: orthorhombic, cubic (equal
@@ -584,7 +598,9 @@ __device__ __forceinline__ float cubic_d32(const PairK<float> &k, const float *t
 }
 
 // FP64 form: ci = b_i = csig a_i and cj = csig a_j, u = (b_i - csig a_j) / s.
-template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT>
+// (NEAR and GLOB are properties of the FP32 form; the FP64 form always checks
+// the rows.)
+template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT, bool NEAR = false, bool GLOB = false>
 __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *tab, const double *__restrict__ tabg,
                                           double m, double ai, double ci, double aj, double cj, double &phi,
                                           double &dqi, double &dqj)
@@ -639,8 +655,10 @@ __device__ __forceinline__ void pair_eval(const PairK<double> &k, const double *
 // dq_i = gD r + Z ej, dq_j = gD r - Z ei, Z = gS (u / s) / s.
 // The LDS rows are read and interpolated for every pair; one compare
 // (t_D >= K - 1) sends the pairs beyond them to a second pass with the
-// global table or the asymptote, which few pairs take.
-template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT>
+// global table or the asymptote, which few pairs take.  NEAR: the caller has
+// shown t_D < K - 1 for every pair (a bound over the two tiles' boxes and
+// q ranges), so the LDS cell is read unclamped and nothing is checked.
+template <bool ADJ, bool JSIDE, int NSIG, bool SPLIT, bool NEAR = false, bool GLOB = false>
 __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *tab, const float *__restrict__ tabg,
                                           float m, float ai, float ci, float ej, float ei, float &phi, float &dqi,
                                           float &dqj)
@@ -677,17 +695,28 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
     // SPLIT (the image kernels, where many pairs lie beyond the LDS rows):
     // each lane reads one table source, the LDS rows (t_D < K - 1, so the
     // cell's rows kk and kk + 1 are both there), the global rows, or the
-    // asymptote, and a wavefront runs only the sources its lanes need
-    if (SPLIT) {
+    // asymptote, and a wavefront runs only the sources its lanes need.
+    // GLOB: the caller has shown K - 1 <= t_D < n_D - 1 for every pair, so
+    // every lane reads the global rows with no branch (the loads of a step's
+    // pairs can then be issued together)
+    if (NEAR) {
+        const float *t = tab + (__umul24((unsigned)kk, (unsigned)S) + (unsigned)l);
+        bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
+    } else if (GLOB) {
+        // the cell's corners in one 16-byte load; the table has no column
+        // beyond n_sigma - 1: last cell and its fraction
+        const int lg = min(l, nS - 2);
+        const float4 c = k.quad[(uint32_t)(kk * (nS - 1) + lg)];
+        bilinear<float, ADJ, JSIDE>(c.x, c.y, c.z, c.w, fD, ts - (float)lg, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
+    } else if (SPLIT) {
         if (tD < k.tDlds) {
             const float *t = tab + (__umul24((unsigned)kk, (unsigned)S) + (unsigned)l);
             bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
         } else if (tD < k.tDmax) {
-            // global rows have no extra column: last cell and its fraction
             const int lg = min(l, nS - 2);
-            const float *t0 = tabg + (uint32_t)(kk * nS + lg);
-            bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, 1.0f, ei,
-                                        ej, phi, dqi, dqj);
+            const float4 c = k.quad[(uint32_t)(kk * (nS - 1) + lg)];
+            bilinear<float, ADJ, JSIDE>(c.x, c.y, c.z, c.w, fD, ts - (float)lg, r, u, inv, 1.0f, ei, ej, phi, dqi,
+                                        dqj);
         } else {
             asymptote<float, ADJ, JSIDE>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
         }
@@ -731,8 +760,10 @@ __device__ __forceinline__ void kadd(R &sum, R &c, R y)
 // and the j-side sums rotate with the records.  MASK applies the distance cut
 // pair by pair (only for tiles that straddle it).  NORM (FP32 on cubic
 // grids) takes the squared distance from the exact integer form of dist2n,
-// with |x_j|^2 rotating along.
-template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, int GEO, int IPL, bool SPLIT>
+// with |x_j|^2 rotating along.  NEAR: every pair of the ring lies below the
+// LDS rows; GLOB: every pair lies in the global rows (see pair_eval).
+template <typename R, bool ADJ, bool MASK, bool KAHAN, int NSIG, int GEO, int IPL, bool SPLIT, bool NEAR = false,
+          bool GLOB = false>
 __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R *__restrict__ tabg, R rcm,
                                        const R (&sx)[IPL], const R (&sy)[IPL], const R (&sz)[IPL], const R (&ai)[IPL],
                                        const R (&ci)[IPL], const R (&ni)[IPL], R xj, R yj, R zj, R wj, R aj, R nj,
@@ -777,7 +808,8 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
             } else
                 m = dist2<R, GEO>(kc, sx[p] - xj, sy[p] - yj, sz[p] - zj);
             R ph, q = 0, jq = 0;
-            pair_eval<ADJ, true, NSIG, SPLIT>(kc, tab, tabg, m, ai[p], ci[p], aj, F32 ? ei[p] : cj_, ph, q, jq);
+            pair_eval<ADJ, true, NSIG, SPLIT, NEAR, GLOB>(kc, tab, tabg, m, ai[p], ci[p], aj, F32 ? ei[p] : cj_, ph, q,
+                                                          jq);
             R wjp = nj, wip = ni[p];
             if (MASK) {
                 wjp = (m <= rcm) ? nj : (R)0;
@@ -912,7 +944,8 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                                                             const int64_t *__restrict__ hdr, int *__restrict__ counter,
                                                             const R *__restrict__ tabg, const int *__restrict__ imgs,
                                                             const int64_t *__restrict__ rowoff,
-                                                            double *__restrict__ ipart, double *__restrict__ jpart)
+                                                            double *__restrict__ ipart, double *__restrict__ jpart,
+                                                            const float4 *__restrict__ quad)
 {
     using Rec = typename RecOf<R>::T;
     constexpr int NJc = 1 + (IMG ? 1 : 0) + (ADJ ? 1 : 0);
@@ -939,6 +972,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
     kc.nS = nS;
     kc.K = A.K;
     kc.nD = A.nD;
+    kc.quad = quad;
 
     for (int t = threadIdx.x; t < A.K * nS; t += TPB) {
         int r = t / nS, c = t - r * nS;
@@ -1078,8 +1112,27 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
             // off-diagonal item: both orders of every pair, j tiles rotating through the lanes
             const int J0 = (I + 1) * BI + (c - A.ND) * A.JC, J1 = min(N, J0 + A.JC);
             const bool prune = IMG && A.rc2 < 1e300;
+            // FP32 bilinear image kernels: rings whose pairs provably stay
+            // below the LDS rows take the NEAR ring (bound from the tile boxes
+            // and the largest a of either tile, widened by 2^-10 for the FP32
+            // rounding of s r); without images the plain ring was as fast
+            constexpr bool NEARABLE = sizeof(R) == 4 && NSIG != kCubicD && IMG;
+            // image kernels: rings whose pairs provably lie in the global rows
+            // (K - 1 <= t_D < n_D - 1) take the GLOB ring
+            constexpr bool GLOBABLE = NEARABLE && IMG;
             R ib[6] = {0, 0, 0, 0, 0, 0};
-            if (prune) {
+            R aimax = 0, aimin = 0;
+            if (NEARABLE) {
+                R am = ai[0], an = ai[0];
+#pragma unroll
+                for (int p = 1; p < IPL; ++p) {
+                    am = max(am, ai[p]);
+                    an = min(an, ai[p]);
+                }
+                aimax = uniform(wave_max<R>(am));
+                aimin = uniform(wave_min<R>(an));
+            }
+            if (prune || NEARABLE) {
                 // bounding box of this wavefront's i-points
                 R lo[3], hi[3];
                 box_pos<R, GEO>(kc, Ir[0].x, Ir[0].y, Ir[0].z, lo[0], lo[1], lo[2]);
@@ -1105,7 +1158,9 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 const bool jv = jj < J1;
                 const Rec Jr = P[jv ? jj : J1 - 1];
                 R jb6[6] = {0, 0, 0, 0, 0, 0};
-                if (prune) {
+                const R ajmax = NEARABLE ? uniform(wave_max<R>(Jr.a)) : (R)0;
+                const R ajmin = GLOBABLE ? uniform(wave_min<R>(Jr.a)) : (R)0;
+                if (prune || NEARABLE) {
                     R q[3];
                     box_pos<R, GEO>(kc, Jr.x, Jr.y, Jr.z, q[0], q[1], q[2]);
                     jb6[0] = uniform(wave_min<R>(q[0]));
@@ -1121,18 +1176,27 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 for (int L = 0; L < nimg; ++L) {
                     R lx = 0, ly = 0, lz = 0;
                     bool home = true, masked = prune;  // no cut: every tile unmasked
+                    bool near = false, glob = false;
                     if (IMG) {
                         lx = (R)(imgs[4 * L + 0] * sg.nx);
                         ly = (R)(imgs[4 * L + 1] * sg.ny);
                         lz = (R)(imgs[4 * L + 2] * sg.nz);
                         home = (L == A.home);
+                    }
+                    if (prune || NEARABLE) {
+                        // r_i - r_j - L: the j box shifted by +L against the i box
+                        R dmin2, dmax2, bx, by, bz;
+                        box_pos<R, GEO>(kc, lx, ly, lz, bx, by, bz);
+                        box_dist2<R, GEO == kSkew>(kc, ib, jb6, bx, by, bz, dmin2, dmax2);
                         if (prune) {
-                            // r_i - r_j - L: the j box shifted by +L against the i box
-                            R dmin2, dmax2, cx, cy, cz;
-                            box_pos<R, GEO>(kc, lx, ly, lz, cx, cy, cz);
-                            box_dist2<R, GEO == kSkew>(kc, ib, jb6, cx, cy, cz, dmin2, dmax2);
                             if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
                             masked = dmax2 > rcm;
+                        }
+                        if (NEARABLE) {
+                            const R hi = (aimax + ajmax) * sqrt(dmax2) * (R)(1.0 + 1.0 / 1024.0);
+                            near = hi < kc.tDlds;
+                            glob = GLOBABLE && hi < kc.tDmax &&
+                                   (aimin + ajmin) * sqrt(dmin2) * (R)(1.0 - 1.0 / 1024.0) >= kc.tDlds;
                         }
                     }
                     R sx[IPL], sy[IPL], sz[IPL], acc[IPL], accq[IPL];
@@ -1145,14 +1209,19 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                     }
                     R accj = 0, accqj = 0;
                     const R nj0 = jv ? Jr.n : (R)0;
-                    if (masked)
-                        ring64<R, ADJ, true, KAHAN, NSIG, GEO, IPL, IMG>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
-                                                                      Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
-                                                                      accqj);
-                    else
-                        ring64<R, ADJ, false, KAHAN, NSIG, GEO, IPL, IMG>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x,
-                                                                       Jr.y, Jr.z, Jr.w, Jr.a, nj0, acc, accq, accj,
-                                                                       accqj);
+#define RING(MSK, NR, GL)                                                                                          \
+    ring64<R, ADJ, MSK, KAHAN, NSIG, GEO, IPL, IMG, NR, GL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x, Jr.y, Jr.z, \
+                                                         Jr.w, Jr.a, nj0, acc, accq, accj, accqj)
+                    if (masked) {
+                        if (NEARABLE && near) RING(true, NEARABLE, false);
+                        else if (GLOBABLE && glob) RING(true, false, GLOBABLE);
+                        else RING(true, false, false);
+                    } else {
+                        if (NEARABLE && near) RING(false, NEARABLE, false);
+                        else if (GLOBABLE && glob) RING(false, false, GLOBABLE);
+                        else RING(false, false, false);
+                    }
+#undef RING
 #pragma unroll
                     for (int p = 0; p < IPL; ++p) {
                         if (home) Sc[p] += (double)acc[p];
@@ -1539,9 +1608,10 @@ __global__ __launch_bounds__(256) void grad_q0_batched_kernel(const Seg *__restr
 // ---------------------------------------------------------------------------
 
 struct Layout {
-    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, qmin, vox, dEdq,
-        fartab, far, total;
+    size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, qmin, quad, vox,
+        dEdq, fartab, far, total;
     int64_t nblocks, slots, rows, fin_blocks, Gtot;
+    int64_t quad_cells;  // FP32 image runs: cells of the global table held as corner quadruples
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1618,8 +1688,8 @@ constexpr int64_t kCUs = 256;
 // layout of any n_sigma).
 int plan_nsig(const vdw_table_params *tp) { return tp->interp == VDW_INTERP_CUBIC_D ? kCubicD : tp->n_sigma; }
 
-int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int nsig, int fp64, int adj,
-              Plan *P)
+int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_opts *o, int nsig, int nD, int fp64,
+              int adj, Plan *P)
 {
     P->segs.resize(B);
     P->gds.resize(B);
@@ -1834,6 +1904,9 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     off = align256(off + (4 * B + 1) * sizeof(double));
     L.qmin = off;
     off = align256(off + B * sizeof(uint64_t));
+    L.quad = off;
+    L.quad_cells = (!fp64 && P->img && nsig > 0) ? (int64_t)(nD - 1) * (nsig - 1) : 0;
+    off = align256(off + (size_t)L.quad_cells * sizeof(float4));
     L.vox = off;
     if (o->self_term == 2) off = align256(off + (size_t)B * kVoxNodes * sizeof(double));
     L.dEdq = off;
@@ -1862,6 +1935,7 @@ int validate_opts(const vdw_opts *o)
 }
 
 struct PairPtrs {
+    const float4 *quad;
     const void *recs;
     const Seg *segs;
     const int64_t *hdr;
@@ -1883,7 +1957,7 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
     if (attr_only) return VDW_OK;
     hipLaunchKernelGGL((pair_kernel<R, ADJ, IMG, KAHAN, NSIG, GEO, IPL, TPB>), dim3(grid), dim3(TPB), lds, s, a,
                        (const typename RecOf<R>::T *)p.recs, p.segs, p.hdr, p.counter, (const R *)p.tabg, p.imgs,
-                       p.rowoff, p.ipart, (double *)p.jpart);
+                       p.rowoff, p.ipart, (double *)p.jpart, p.quad);
     VDW_HIP(hipGetLastError());
     return VDW_OK;
 }
@@ -1995,7 +2069,7 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     E->self_term = o->self_term;
     E->interp = tp->interp;
     E->n_cut = o->n_cut;
-    rc = make_plan(B, grids, grid_off, o, plan_nsig(tp), E->fp64, adj, &E->P);
+    rc = make_plan(B, grids, grid_off, o, plan_nsig(tp), tp->n_D, E->fp64, adj, &E->P);
     if (rc) return rc;
     const Plan &P = E->P;
     if (ws_bytes < P.L.total) return fail(VDW_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, P.L.total);
@@ -2165,6 +2239,14 @@ int enqueue(const Exec &E, const double *n_d, const double *q0_d, const double *
 
     // pair kernel
     PairPtrs pp;
+    pp.quad = nullptr;
+    if (L.quad_cells > 0) {
+        float4 *quad = (float4 *)(w + L.quad);
+        hipLaunchKernelGGL(quad_kernel, dim3((unsigned)((L.quad_cells + 255) / 256)), dim3(256), 0, s, phi_f, quad,
+                           E.nD, E.nsig);
+        VDW_HIP(hipGetLastError());
+        pp.quad = quad;
+    }
     pp.recs = recs;
     pp.segs = segs;
     pp.hdr = hdr;
@@ -2424,7 +2506,7 @@ extern "C" size_t enl_batched_workspace_size(int32_t B, const vdw_grid *grids, c
 {
     if (B < 1 || !grids || validate_opts(opts) || validate_table(tp)) return 0;
     Plan P;
-    if (make_plan(B, grids, nullptr, opts, plan_nsig(tp), opts->precision == VDW_FP64, 1, &P)) return 0;
+    if (make_plan(B, grids, nullptr, opts, plan_nsig(tp), tp->n_D, opts->precision == VDW_FP64, 1, &P)) return 0;
     return P.L.total;
 }
 
