@@ -331,3 +331,29 @@ def test_batch_matches_oracle(V, oracle, big):
         ref = oracle.potential_at(oracle.Grid(m.n, m.h), m.rho, ks, tab, tp, m.n_cut)
         v = vb[offs[b]:offs[b + 1]][ks]
         assert np.linalg.norm(v - ref) <= vtol * np.linalg.norm(ref), b
+
+
+def test_batch_fp32c_and_kahan_against_fp64(V, big):
+    """The 64-molecule batch in FP32C, plain and Kahan-compensated, against the
+    FP64 form, molecule by molecule.  Several molecules' totals nearly cancel
+    (a negative pair energy against a positive on-site term), so the error is
+    measured against the sum of the components' magnitudes,
+    |E_pair0| + |E_pairL| + |E_self|, the scale the FP32 roundings act on:
+    within 1e-6 of it for both forms.  The largest error relative to |E|
+    itself is printed."""
+    tp, tab = big
+    table = _gpu_table(V, tp, tab)
+    mols = W.molecule_batch(64)
+    grids, ns, n, offs, qd = _batch(V, mols)
+    E64, _ = V.enl_potential_batched(grids, n, offs, qd, table, V.Opts(n_cut=mols[0].n_cut, precision=0))
+    for kahan in (0, 1):
+        E32, _ = V.enl_potential_batched(grids, n, offs, qd, table,
+                                         V.Opts(n_cut=mols[0].n_cut, precision=1, kahan=kahan))
+        worst_scale = worst_total = 0.0
+        for b in range(len(mols)):
+            scale = sum(abs(x) for x in E64[b])
+            d = abs(sum(E32[b]) - sum(E64[b]))
+            worst_scale = max(worst_scale, d / scale)
+            worst_total = max(worst_total, d / abs(sum(E64[b])))
+            assert d <= 1e-6 * scale, (kahan, b, E32[b], E64[b])
+        say(f"batch kahan={kahan}: max |dE| / sum|E_c| = {worst_scale:.2e}, max |dE| / |E| = {worst_total:.2e}")
