@@ -362,6 +362,9 @@ def main():
         dt64, E64, v64, kms64, _ = timed(V.VDW_FP64, steps64, 1)
         rate64 = pairs * steps64 / dt64
         dE = max(abs(sum(e32) - sum(e64)) / abs(sum(e64)) for e32, e64 in zip(E32, E64))
+        # the same error over |E_pair0| + |E_pairL| + |E_self|: the scale of the FP32
+        # roundings, apart when a density's components nearly cancel
+        dEc = max(abs(sum(e32) - sum(e64)) / sum(abs(x) for x in e64) for e32, e64 in zip(E32, E64))
         dv = float(torch.linalg.norm(v32 - v64) / torch.linalg.norm(v64))
         ach64 = 0.5 * near_pairs * FLOP_PER_UNORDERED_PAIR / (kms64 * 1e-3) / 1e12
         passed = bool(dE <= GATE_DE_REL and dv <= GATE_DV_REL)
@@ -373,7 +376,8 @@ def main():
                                 "against": "GPU FP64 form, every density of the step"}
         out["fp64"] = {"value": rate64, "ms_per_step": 1e3 * dt64 / steps64, "kernel_ms": kms64,
                        "speedup_fp32c_over_fp64": value / rate64,
-                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dv_rel_l2": dv, "within_gate": passed},
+                       "fp32c_vs_fp64": {"dE_rel_max": dE, "dE_rel_max_of_components": dEc, "dv_rel_l2": dv,
+                                         "within_gate": passed},
                        "roofline": {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                                     "frac": ach64 / PEAK_FP64_TFLOPS,
                                     "kernel": "pair_kernel<double, ADJ, %s>" % (
