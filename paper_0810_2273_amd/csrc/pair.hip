@@ -427,7 +427,7 @@ struct PairK {
     R en[9];
     int S, nS, K;
     int nD;           // table rows
-    // FP32 image kernels: the global table as one float4 per cell, the
+    // FP32 bilinear kernels: the global table as one float4 per cell, the
     // corners (k, l), (k, l+1), (k+1, l), (k+1, l+1) of cell k (n_sigma - 1) + l
     const float4 *quad;
 };
@@ -722,16 +722,17 @@ __device__ __forceinline__ void pair_eval(const PairK<float> &k, const float *ta
         }
     } else {
         // every lane reads the LDS copy (the clamped read is in bounds); the
-        // pairs beyond it are redone from the global rows or the asymptote
+        // pairs beyond it are redone from the global rows (the cell's corner
+        // quadruple, one 16-byte load) or the asymptote
         const int kl = min(kk, k.K - 2);
         const float *t = tab + (__umul24((unsigned)kl, (unsigned)S) + (unsigned)l);
         bilinear<float, ADJ, JSIDE>(t[0], t[1], t[S], t[S + 1], fD, fS, r, u, inv, 1.0f, ei, ej, phi, dqi, dqj);
         if (tD >= k.tDlds) {
             if (tD < k.tDmax) {
                 const int lg = min(l, nS - 2);
-                const float *t0 = tabg + (uint32_t)(kk * nS + lg);
-                bilinear<float, ADJ, JSIDE>(t0[0], t0[1], t0[nS], t0[nS + 1], fD, ts - (float)lg, r, u, inv, 1.0f,
-                                            ei, ej, phi, dqi, dqj);
+                const float4 c = k.quad[(uint32_t)(kk * (nS - 1) + lg)];
+                bilinear<float, ADJ, JSIDE>(c.x, c.y, c.z, c.w, fD, ts - (float)lg, r, u, inv, 1.0f, ei, ej, phi, dqi,
+                                            dqj);
             } else {
                 asymptote<float, ADJ, JSIDE>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
             }
@@ -1611,7 +1612,7 @@ struct Layout {
     size_t hdr, counter, flag, segs, imgs, counts, rowoff, recs, gidx, ipart, jpart, blockE, res, qmin, quad, vox,
         dEdq, fartab, far, total;
     int64_t nblocks, slots, rows, fin_blocks, Gtot;
-    int64_t quad_cells;  // FP32 image runs: cells of the global table held as corner quadruples
+    int64_t quad_cells;  // FP32 bilinear runs: cells of the global table held as corner quadruples
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1905,7 +1906,7 @@ int make_plan(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_o
     L.qmin = off;
     off = align256(off + B * sizeof(uint64_t));
     L.quad = off;
-    L.quad_cells = (!fp64 && P->img && nsig > 0) ? (int64_t)(nD - 1) * (nsig - 1) : 0;
+    L.quad_cells = (!fp64 && nsig > 0) ? (int64_t)(nD - 1) * (nsig - 1) : 0;
     off = align256(off + (size_t)L.quad_cells * sizeof(float4));
     L.vox = off;
     if (o->self_term == 2) off = align256(off + (size_t)B * kVoxNodes * sizeof(double));
