@@ -865,18 +865,46 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
     }
 }
 
-// Wavefront-wide min / max (every lane gets the result).
+// Wavefront-wide min / max (every lane gets the result; all 64 lanes active).
+// FP32: rotations within each row of 16 lanes (DPP row_ror 8, 4, 2, 1) leave
+// every lane with its row's result, then the four rows are read out, all
+// without the LDS unit; FP64: lane exchanges.
+template <int CTRL>
+__device__ inline float dpp_row(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float lane_value(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
 template <typename R>
 __device__ inline R wave_min(R v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, (R)__shfl_xor(v, o));
-    return v;
+    if constexpr (sizeof(R) == 4) {
+        v = min(v, dpp_row<0x128>(v));
+        v = min(v, dpp_row<0x124>(v));
+        v = min(v, dpp_row<0x122>(v));
+        v = min(v, dpp_row<0x121>(v));
+        return min(min(lane_value(v, 0), lane_value(v, 16)), min(lane_value(v, 32), lane_value(v, 48)));
+    } else {
+        for (int o = 32; o > 0; o >>= 1) v = min(v, (R)__shfl_xor(v, o));
+        return v;
+    }
 }
 template <typename R>
 __device__ inline R wave_max(R v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, (R)__shfl_xor(v, o));
-    return v;
+    if constexpr (sizeof(R) == 4) {
+        v = max(v, dpp_row<0x128>(v));
+        v = max(v, dpp_row<0x124>(v));
+        v = max(v, dpp_row<0x122>(v));
+        v = max(v, dpp_row<0x121>(v));
+        return max(max(lane_value(v, 0), lane_value(v, 16)), max(lane_value(v, 32), lane_value(v, 48)));
+    } else {
+        for (int o = 32; o > 0; o >>= 1) v = max(v, (R)__shfl_xor(v, o));
+        return v;
+    }
 }
 
 // A wavefront-uniform copy of lane 0's value.  The builtin moves 32-bit
