@@ -774,20 +774,29 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
     // square grids: x, y exactly as NORM (|x_i|^2 + |x_j|^2 - 2 x_i . x_j over
     // x and y), then the z term w_z (z_i - z_j)^2
     constexpr bool SQXY = GEO == kSquare && sizeof(R) == 4;
+    // FP64 on cubic grids: the same exact integer as NORM, formed in FP32 and
+    // widened (it equals the FP64 difference form bit for bit); the j
+    // coordinates travel as one f16 pair and two FP32 values
+    constexpr bool NORM64 = GEO == kCubic && sizeof(R) == 8;
+    constexpr bool XY16 = NORM || SQXY || NORM64;
     R mz[IPL], wi[IPL], ca[IPL], cq[IPL];
+    float mz32[IPL], wi32[IPL];
     half2v mxy[IPL];
 #pragma unroll
     for (int p = 0; p < IPL; ++p) {
-        if (NORM || SQXY) mxy[p] = half2v{(_Float16)(float)(-2 * sx[p]), (_Float16)(float)(-2 * sy[p])};
+        if (XY16) mxy[p] = half2v{(_Float16)(float)(-2 * sx[p]), (_Float16)(float)(-2 * sy[p])};
         mz[p] = -2 * sz[p];
         wi[p] = SQXY ? sx[p] * sx[p] + sy[p] * sy[p] : sx[p] * sx[p] + sy[p] * sy[p] + sz[p] * sz[p];
+        mz32[p] = (float)mz[p];
+        wi32[p] = (float)wi[p];
         ca[p] = 0;  // Kahan terms (KAHAN only)
         cq[p] = 0;
     }
-    // NORM, SQXY: the x, y coordinates of the j records as one f16 pair; SQXY
-    // carries x_j^2 + y_j^2 in wj
-    half2v xyj = (NORM || SQXY) ? half2v{(_Float16)(float)xj, (_Float16)(float)yj} : half2v{};
+    // NORM, SQXY, NORM64: the x, y coordinates of the j records as one f16
+    // pair; SQXY carries x_j^2 + y_j^2 in wj
+    half2v xyj = XY16 ? half2v{(_Float16)(float)xj, (_Float16)(float)yj} : half2v{};
     if (SQXY) wj = xj * xj + yj * yj;
+    float zj32 = (float)zj, wj32 = (float)wj;
     // FP32: the j point travels as ej = 4 csig a_j, the i points also carry ei
     constexpr bool F32 = sizeof(R) == 4;
     R ei[IPL];
@@ -803,6 +812,8 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
             R m;
             if (NORM)
                 m = (R)__builtin_amdgcn_fdot2(mxy[p], xyj, fmaf((float)mz[p], (float)zj, (float)(wi[p] + wj)), false);
+            else if (NORM64)
+                m = (R)__builtin_amdgcn_fdot2(mxy[p], xyj, fmaf(mz32[p], zj32, wi32[p] + wj32), false);
             else if (SQXY) {
                 const float dz = (float)sz[p] - (float)zj;
                 m = (R)fmaf((float)kc.wz * dz, dz, __builtin_amdgcn_fdot2(mxy[p], xyj, (float)(wi[p] + wj), false));
@@ -836,14 +847,19 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
             kadd(accj, cj, sj);
             if (ADJ) kadd(accqj, cqj, sqj);
         }
-        if (NORM || SQXY) {
+        if (XY16) {
             xyj = wrot(xyj);
         } else {
             xj = wrot(xj);
             yj = wrot(yj);
         }
-        zj = wrot(zj);
-        if (NORM || SQXY) wj = wrot(wj);
+        if (NORM64) {
+            zj32 = wrot(zj32);
+            wj32 = wrot(wj32);
+        } else {
+            zj = wrot(zj);
+            if (NORM || SQXY) wj = wrot(wj);
+        }
         aj = wrot(aj);
         nj = wrot(nj);
         accj = wrot(accj);
@@ -2044,9 +2060,11 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
         if (nsig == 64) return launch_pair_v<float, false, 64, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
         return launch_pair_v<float, false, 0, kSkew>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     }
-    if (fp64)
-        return cubd ? launch_pair_v<double, false, kCubicD, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only)
-                    : launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (fp64) {
+        if (cubd) return launch_pair_v<double, false, kCubicD, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        return geo == kCubic ? launch_pair_v<double, false, 0, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                             : launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    }
     if (kahan) return launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (nsig == 64)
         return geo == kCubic    ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
