@@ -9,11 +9,12 @@
 //   far_table  one thread per displacement: the shell's lattice sum in
 //              FP64, in a fixed order
 //   far_rows   one lane per kept point i (two per thread), the j-points of
-//              one chunk of the density streamed through scalar loads; T
-//              gathered at the displacement (the lanes of a wavefront are
-//              one brick of points, so their gathers hit a few cache
-//              lines); FP64 sums per chunk, the pair i = j included; the
-//              chunk partials are added in a fixed order later
+//              one chunk of the density streamed through scalar loads in
+//              tiles; T read from an LDS copy of the tile's displacement
+//              box (or gathered where the box is too large); FP64 sums per
+//              chunk, the pair i = j included; the chunk partials are added
+//              in a fixed order later
+#include <limits.h>
 #include <math.h>
 
 #include "common.h"
@@ -64,9 +65,40 @@ __device__ inline double rcp64(double x)
 
 // Rows of block x, j chunk y (of gridDim.y): partial sums of the chunk's
 // j-points, written to part[y][i] (energy) and (ADJ) part[C + y][i]
-// (dE/da_i).  The j loop takes groups of kFarJ points so that their table
-// gathers are in flight together.
+// (dE/da_i).  The j-points go in tiles of kFarTile consecutive records: the
+// displacements between the block's i-points and a tile's j-points fill a
+// box of the grid displacements, which the block copies from T into LDS
+// (one coalesced pass) when it holds at most kFarStage entries, so each pair
+// reads T from LDS; a tile whose box is larger (scattered points) gathers T
+// directly, kFarJ j-points at a time so that their gathers are in flight
+// together.  Either way the j-points are summed in their order.
 constexpr int kFarJ = 4;
+constexpr int kFarTile = 64;
+constexpr int kFarStage = 4096;  // FP64 entries (32 KiB of LDS)
+
+// Block-wide min and max of six integers (every thread gets them); `red`
+// holds kFarThreads / 64 x 6 values.
+__device__ inline void block_box(int (&v)[6], int *red)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int x = v[k];
+        for (int o = 32; o > 0; o >>= 1) {
+            const int y = __shfl_xor(x, o);
+            x = (k & 1) ? max(x, y) : min(x, y);
+        }
+        if (lane == 0) red[w * 6 + k] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int x = red[k];
+        for (int u = 1; u < kFarThreads / 64; ++u) x = (k & 1) ? max(x, red[u * 6 + k]) : min(x, red[u * 6 + k]);
+        v[k] = x;
+    }
+    __syncthreads();
+}
 
 template <typename Rec, bool ADJ>
 __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const Rec *__restrict__ recs,
@@ -76,10 +108,12 @@ __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const R
                                                                double qscale, int64_t stride,
                                                                double *__restrict__ part)
 {
+    __shared__ double Ts[kFarStage];
+    __shared__ int red[(kFarThreads / 64) * 6];
     const int64_t N = *nkept;
     recs += *first;
     const int64_t i0 = (int64_t)blockIdx.x * (kFarThreads * kFarIPL);
-    if (i0 >= N) return;  // N >= 1 below
+    if (i0 >= N) return;  // N >= 1 below (the whole block leaves together)
     const int C = gridDim.y, c = blockIdx.y;
     const int64_t len = (N + C - 1) / C;
     const int64_t j0 = min(N, (int64_t)c * len), j1 = min(N, j0 + len);
@@ -87,20 +121,31 @@ __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const R
     // `off` is its x + ex (y + ey z)
     const int ex = 2 * g.nx - 1, ey = 2 * g.ny - 1;
     const int k0 = (g.nx - 1) + ex * ((g.ny - 1) + ey * (g.nz - 1));
-    int base[kFarIPL];
+    int base[kFarIPL], ix[kFarIPL], iy[kFarIPL], iz[kFarIPL];
     double pi[kFarIPL], g2[kFarIPL], a2[kFarIPL], acc[kFarIPL], accq[kFarIPL];
+    int ib[6] = {INT_MAX, INT_MIN, INT_MAX, INT_MIN, INT_MAX, INT_MIN};
 #pragma unroll
     for (int p = 0; p < kFarIPL; ++p) {
         const int64_t i = i0 + threadIdx.x + (int64_t)kFarThreads * p;
         const Rec R = recs[i < N ? i : N - 1];
         // table entry of displacement r_i - r_j is base - off(j)
         base[p] = rec_off(R) + k0;
+        ix[p] = (int)R.x;
+        iy[p] = (int)R.y;
+        iz[p] = (int)R.z;
+        ib[0] = min(ib[0], ix[p]);
+        ib[1] = max(ib[1], ix[p]);
+        ib[2] = min(ib[2], iy[p]);
+        ib[3] = max(ib[3], iy[p]);
+        ib[4] = min(ib[4], iz[p]);
+        ib[5] = max(ib[5], iz[p]);
         const double a = (double)R.a;
         pi[p] = a * a;
         g2[p] = 2.0 / a;
         a2[p] = 2.0 * a;
         acc[p] = accq[p] = 0.0;
     }
+    block_box(ib, red);  // the block's i box (padding lanes repeat point N - 1)
     // one pair: w = n_j T / (p_i p_j (p_i + p_j)); d/da_i of -1 / (a_i^2 a_j^2 pp)
     // is (2 / a_i + 2 a_i / pp) / (a_i^2 a_j^2 pp)
     auto term = [&](int p, double t, double pj, double nj) {
@@ -110,33 +155,91 @@ __global__ __launch_bounds__(kFarThreads) void far_rows_kernel(FarGeo g, const R
         acc[p] += w;
         if (ADJ) accq[p] += w * (g2[p] + a2[p] * (Rinv * X));
     };
-    int64_t j = j0;
-    for (; j + kFarJ <= j1; j += kFarJ) {
-        int oj[kFarJ];
-        double pj[kFarJ], nj[kFarJ], t[kFarJ][kFarIPL];
-#pragma unroll
-        for (int u = 0; u < kFarJ; ++u) {
-            const Rec J = recs[j + u];
-            oj[u] = rec_off(J);
-            const double aj = (double)J.a;
-            pj[u] = aj * aj;
-            nj[u] = (double)J.n;
+    for (int64_t jt = j0; jt < j1; jt += kFarTile) {
+        const int64_t je = min(j1, jt + kFarTile);
+        // the tile's j box, then the displacement box r_i - r_j
+        int jb[6];
+        {
+            const int64_t jj = jt + (threadIdx.x & 63);
+            const Rec J = recs[jj < je ? jj : je - 1];
+            jb[0] = jb[1] = (int)J.x;
+            jb[2] = jb[3] = (int)J.y;
+            jb[4] = jb[5] = (int)J.z;
         }
+        block_box(jb, red);
+        const int dx0 = ib[0] - jb[1], dy0 = ib[2] - jb[3], dz0 = ib[4] - jb[5];
+        const int bx = ib[1] - jb[0] - dx0 + 1, by = ib[3] - jb[2] - dy0 + 1, bz = ib[5] - jb[4] - dz0 + 1;
+        const bool staged = (int64_t)bx * by * bz <= kFarStage;
+        if (staged) {
+            const int vol = bx * by * bz, bxy = bx * by;
+            for (int e = threadIdx.x; e < vol; e += kFarThreads) {
+                const int ez = e / bxy, r = e - ez * bxy, ey_ = r / bx, ex_ = r - ey_ * bx;
+                Ts[e] = T[(unsigned)((dx0 + ex_) + ex * ((dy0 + ey_) + ey * (dz0 + ez)) + k0)];
+            }
+            __syncthreads();
+            // local index of r_i - r_j in the box: Li - Lj
+            int Li[kFarIPL];
 #pragma unroll
-        for (int u = 0; u < kFarJ; ++u)
+            for (int p = 0; p < kFarIPL; ++p) Li[p] = (ix[p] - dx0) + bx * ((iy[p] - dy0) + by * (iz[p] - dz0));
+            int64_t j = jt;
+            for (; j + kFarJ <= je; j += kFarJ) {
+                int Lj[kFarJ];
+                double pj[kFarJ], nj[kFarJ], t[kFarJ][kFarIPL];
 #pragma unroll
-            for (int p = 0; p < kFarIPL; ++p) t[u][p] = T[(unsigned)(base[p] - oj[u])];
+                for (int u = 0; u < kFarJ; ++u) {
+                    const Rec J = recs[j + u];
+                    Lj[u] = (int)J.x + bx * ((int)J.y + by * (int)J.z);
+                    const double aj = (double)J.a;
+                    pj[u] = aj * aj;
+                    nj[u] = (double)J.n;
+                }
 #pragma unroll
-        for (int u = 0; u < kFarJ; ++u)
+                for (int u = 0; u < kFarJ; ++u)
 #pragma unroll
-            for (int p = 0; p < kFarIPL; ++p) term(p, t[u][p], pj[u], nj[u]);
-    }
-    for (; j < j1; ++j) {
-        const Rec J = recs[j];
-        const int oj = rec_off(J);
-        const double aj = (double)J.a;
+                    for (int p = 0; p < kFarIPL; ++p) t[u][p] = Ts[Li[p] - Lj[u]];
 #pragma unroll
-        for (int p = 0; p < kFarIPL; ++p) term(p, T[(unsigned)(base[p] - oj)], aj * aj, (double)J.n);
+                for (int u = 0; u < kFarJ; ++u)
+#pragma unroll
+                    for (int p = 0; p < kFarIPL; ++p) term(p, t[u][p], pj[u], nj[u]);
+            }
+            for (; j < je; ++j) {
+                const Rec J = recs[j];
+                const int Lj = (int)J.x + bx * ((int)J.y + by * (int)J.z);
+                const double aj = (double)J.a;
+#pragma unroll
+                for (int p = 0; p < kFarIPL; ++p) term(p, Ts[Li[p] - Lj], aj * aj, (double)J.n);
+            }
+            __syncthreads();  // the box is rewritten for the next tile
+        } else {
+            int64_t j = jt;
+            for (; j + kFarJ <= je; j += kFarJ) {
+                int oj[kFarJ];
+                double pj[kFarJ], nj[kFarJ], t[kFarJ][kFarIPL];
+#pragma unroll
+                for (int u = 0; u < kFarJ; ++u) {
+                    const Rec J = recs[j + u];
+                    oj[u] = rec_off(J);
+                    const double aj = (double)J.a;
+                    pj[u] = aj * aj;
+                    nj[u] = (double)J.n;
+                }
+#pragma unroll
+                for (int u = 0; u < kFarJ; ++u)
+#pragma unroll
+                    for (int p = 0; p < kFarIPL; ++p) t[u][p] = T[(unsigned)(base[p] - oj[u])];
+#pragma unroll
+                for (int u = 0; u < kFarJ; ++u)
+#pragma unroll
+                    for (int p = 0; p < kFarIPL; ++p) term(p, t[u][p], pj[u], nj[u]);
+            }
+            for (; j < je; ++j) {
+                const Rec J = recs[j];
+                const int oj = rec_off(J);
+                const double aj = (double)J.a;
+#pragma unroll
+                for (int p = 0; p < kFarIPL; ++p) term(p, T[(unsigned)(base[p] - oj)], aj * aj, (double)J.n);
+            }
+        }
     }
 #pragma unroll
     for (int p = 0; p < kFarIPL; ++p) {
