@@ -2010,8 +2010,9 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 // Instantiated variants: FP32C with n_sigma = 64 on cubic or general
 // orthorhombic grids (the fast paths: without images four i-points per lane
 // in 1024-thread workgroups, or eight in 512-thread ones), FP32C for any
-// n_sigma, Kahan-compensated FP32C, and plain FP64 (two per lane, 1024
-// threads); each with and without the adjoint sums and the image loop.
+// n_sigma, Kahan-compensated FP32C (n_sigma = 64 on cubic grids, any
+// n_sigma elsewhere), and plain FP64 (cubic or orthorhombic; two per lane,
+// 1024 threads); each with and without the adjoint sums and the image loop.
 // Without images every one of them also has 256-thread workgroups with two
 // i-points per lane, for work lists too short to occupy every CU.  Skew
 // cells (FP64, FP32C with n_sigma = 64 or any, Kahan-compensated FP32C) have
@@ -2065,7 +2066,10 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
         return geo == kCubic ? launch_pair_v<double, false, 0, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
                              : launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     }
-    if (kahan) return launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (kahan)
+        return (geo == kCubic && nsig == 64)
+                   ? launch_pair_v<float, true, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
+                   : launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     if (nsig == 64)
         return geo == kCubic    ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
                : geo == kSquare ? launch_pair_v<float, false, 64, kSquare>(adj, img, tpb, a, p, grid, lds, s, attr_only)
