@@ -2010,8 +2010,8 @@ int launch_pair_t(const PairArgs &a, const PairPtrs &p, int grid, size_t lds, hi
 // Instantiated variants: FP32C with n_sigma = 64 on cubic or general
 // orthorhombic grids (the fast paths: without images four i-points per lane
 // in 1024-thread workgroups, or eight in 512-thread ones), FP32C for any
-// n_sigma, Kahan-compensated FP32C (n_sigma = 64 on cubic grids, any
-// n_sigma elsewhere), and plain FP64 (cubic or orthorhombic; two per lane,
+// n_sigma, Kahan-compensated FP32C (n_sigma = 64 on cubic and square grids,
+// any n_sigma elsewhere), and plain FP64 (cubic or orthorhombic; two per lane,
 // 1024 threads); each with and without the adjoint sums and the image loop.
 // Without images every one of them also has 256-thread workgroups with two
 // i-points per lane, for work lists too short to occupy every CU.  Skew
@@ -2066,10 +2066,13 @@ int launch_pair(int fp64, int adj, int img, int kahan, int nsig, int geo, int tp
         return geo == kCubic ? launch_pair_v<double, false, 0, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
                              : launch_pair_v<double, false, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
     }
-    if (kahan)
-        return (geo == kCubic && nsig == 64)
-                   ? launch_pair_v<float, true, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
-                   : launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    if (kahan) {
+        if (nsig == 64 && geo == kCubic)
+            return launch_pair_v<float, true, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        if (nsig == 64 && geo == kSquare)
+            return launch_pair_v<float, true, 64, kSquare>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+        return launch_pair_v<float, true, 0, kOrtho>(adj, img, tpb, a, p, grid, lds, s, attr_only);
+    }
     if (nsig == 64)
         return geo == kCubic    ? launch_pair_v<float, false, 64, kCubic>(adj, img, tpb, a, p, grid, lds, s, attr_only)
                : geo == kSquare ? launch_pair_v<float, false, 64, kSquare>(adj, img, tpb, a, p, grid, lds, s, attr_only)
@@ -2195,9 +2198,8 @@ int prepare(int B, const vdw_grid *grids, const int64_t *grid_off, const vdw_tab
     // exact while |2x| <= 2048)
     if (12.0 * cmax * cmax >= 16777216.0 || cmax > 1024.0) E->geo = kOrtho;
     // square grids (h_x = h_y): the x, y part exactly in the same way, its
-    // partial sums below 8 c^2 (FP32 n_sigma = 64 kernels without Kahan runs)
-    if (E->geo == kOrtho && square && !E->fp64 && !E->kahan && E->nsig == 64 && 8.0 * cxy * cxy < 16777216.0 &&
-        cxy <= 1024.0)
+    // partial sums below 8 c^2 (FP32 n_sigma = 64 kernels)
+    if (E->geo == kOrtho && square && !E->fp64 && E->nsig == 64 && 8.0 * cxy * cxy < 16777216.0 && cxy <= 1024.0)
         E->geo = kSquare;
     if (P.skew) E->geo = kSkew;
     PairPtrs none{};
