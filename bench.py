@@ -273,6 +273,7 @@ def main():
             nimg=int(np.prod([2 * m + 1 if per else 1 for m, per in zip(wl.image_max, wl.periodic)])),
             batch=len(wls), verbose=True)
         a.j_chunks, a.block_threads = tuned.j_chunks, tuned.block_threads
+        V.release_workspaces()  # the sweep's largest workspace is not needed again
         print(f"# autotune: block_threads={a.block_threads} j_chunks={a.j_chunks}", file=sys.stderr, flush=True)
     dt, E32, v32, kms32, st = timed(main_prec, a.steps, a.warmup)
     near_pairs = st["pairs"]

@@ -201,6 +201,16 @@ def _workspace(nbytes: int, device, stream=None, ws: torch.Tensor | None = None)
     return buf
 
 
+def release_workspaces():
+    """Drop the cached per-(device, stream) workspaces (they keep the largest
+    size any call needed, e.g. during a tile-shape sweep) and return the
+    memory to the device.  Calls still running on other streams keep theirs
+    until they finish (torch's stream-ordered allocator)."""
+    with _WS_LOCK:
+        _WS.clear()
+    torch.cuda.empty_cache()
+
+
 def enl_workspace_size(grid: Grid, table: Table | TableParams, opts: Opts) -> int:
     tp = (table.params if isinstance(table, Table) else table).c()
     g, o = grid.c(), opts.c()

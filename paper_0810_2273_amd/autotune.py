@@ -20,6 +20,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 import time
 from dataclasses import replace
 
@@ -94,7 +95,7 @@ def tune(run, opts: api.Opts, kept: int, nimg: int = 1, potential: bool = True, 
                 t = min(ms)
                 report[f"{bt}/{jc}"] = t
                 if verbose:
-                    print(f"# autotune block_threads={bt} j_chunks={jc}: {t:.3f} ms", flush=True)
+                    print(f"# autotune block_threads={bt} j_chunks={jc}: {t:.3f} ms", file=sys.stderr, flush=True)
                 if t < best_ms:
                     best, best_ms = (bt, jc), t
     finally:
