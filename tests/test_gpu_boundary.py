@@ -97,6 +97,13 @@ def test_caller_workspace(V, table):
     assert V.enl_energy(g, n, qd["q0"], table, o, ws=ws) == tuple(E1)
     with pytest.raises(L.VdwError):
         V.enl_potential(g, n, qd, table, o, ws=ws[: nbytes // 2])
+    # the cached workspaces can be dropped; the next call allocates again
+    from paper_0810_2273_amd import api
+
+    V.release_workspaces()
+    assert not api._WS
+    E3, v3 = V.enl_potential(g, n, qd, table, o)
+    assert tuple(E3) == tuple(E1) and torch.equal(v3, v1) and api._WS
 
 
 @pytest.mark.parametrize("image_max,r_cut,far", [((3, 3, 0), 30.0, 0), ((4, 4, 0), 30.0, 0), ((1, 1, 0), 0.0, 3)])
