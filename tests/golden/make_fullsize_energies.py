@@ -13,7 +13,9 @@ generators); nothing here runs or reads the HIP library.  The values:
   * the 48 x 48 x 224 Xe-like slab (the Sec. 6.2 monolayer stand-in; Sec. 3
     periodic repetition) with images |m|, |p| <= 3 and r <= 30 bohr: E_pair0,
     E_self, and E_pairL as twice the sum over one of each image pair (m, -m)
-    (the two terms of each pair are equal), one image shift per step.
+    (the two terms of each pair are equal), one image shift per step;
+  * the 64 synthetic molecules of the batch workload, each in full: E_pair0,
+    E_self and the kept count.
 
 The run takes hours on a few cores (the slab's image sum is ~4e12 pair
 evaluations), so every finished step is written at once and a rerun resumes
@@ -87,7 +89,9 @@ def main():
     rule = dict(gl_points=tp.gl_points, graded_levels=tp.graded_levels, kappa=tp.kappa, A0=tp.A0)
     if doc.get("table") != dict(TABLE, **rule):
         doc = {"table": dict(TABLE, **rule), "workloads": {}}
-    doc.setdefault("host", {})[platform.node() or "host"] = _host()
+    # the host of the first run (the dimer and slab sections); later sections
+    # record their own
+    doc.setdefault("host", {}).setdefault(platform.node() or "host", _host())
 
     if os.path.exists(args.cache):
         tab = np.load(args.cache, allow_pickle=False)
@@ -146,9 +150,23 @@ def main():
         _save(doc)
         print(key, "shift", mk, s, "%.0f s" % (time.time() - t), flush=True)
     # E_pairL = 1/2 dV^2 sum_{m != 0} = dV^2 sum over one of each (m, -m), in the order above
-    ent["E_pairL"] = dV2 * sum(ent["shifts"]["%d,%d,%d" % m]["sum"] for m in half)
-    _save(doc)
-    print(key, "E_pairL", ent["E_pairL"], flush=True)
+    if "E_pairL" not in ent:
+        ent["E_pairL"] = dV2 * sum(ent["shifts"]["%d,%d,%d" % m]["sum"] for m in half)
+        _save(doc)
+        print(key, "E_pairL", ent["E_pairL"], flush=True)
+
+    # --- the 64-molecule batch, every molecule in full ---
+    mols = W.molecule_batch()
+    bent = wls.setdefault("molecule_batch", {"count": len(mols), "molecules": [], "host": _host()})
+    for b in range(len(bent["molecules"]), len(mols)):
+        wl = mols[b]
+        g = O.Grid(wl.n, wl.h, wl.periodic)
+        t = time.time()
+        res = O.evaluate(g, wl.rho, tab, tp, wl.n_cut)
+        bent["molecules"].append(dict(E_pair0=res.E_pair0, E_pairL=res.E_pairL, E_self=res.E_self,
+                                      kept=int(res.q0["keep"].sum()), seconds=time.time() - t))
+        _save(doc)
+        print("molecule", b, bent["molecules"][-1], flush=True)
 
 
 if __name__ == "__main__":

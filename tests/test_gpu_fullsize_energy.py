@@ -120,3 +120,36 @@ def test_xe_slab_energy_vs_oracle(V, gold, table, prec):
                      V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec))
     assert V.last_stats()["retained"] == ref["kept"]
     _check_energy(E, ref, prec, "xe slab")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_molecule_batch_energies_vs_oracle(V, gold, table, prec):
+    """The 64-molecule batch in one batched call (the benchmark's launch
+    configuration) against the oracle's energies of every molecule in full.
+    Several molecules nearly cancel (a negative pair energy against a positive
+    on-site term), so the tolerance is relative to |E_pair0| + |E_self|, the
+    scale the roundings act on: FP32C 1e-6, FP64 1e-11 (and FP64 also within
+    1e-10 of |E| itself)."""
+    import torch
+
+    ref = gold["workloads"].get("molecule_batch")
+    if ref is None or len(ref["molecules"]) < ref["count"]:
+        pytest.skip("the oracle's batch energies are not stored yet")
+    mols = W.molecule_batch()
+    assert len(mols) == ref["count"]
+    grids = [V.Grid(m.n, m.h, m.periodic) for m in mols]
+    n, offs = V.pack_batch(grids, [torch.tensor(m.rho.reshape(-1), dtype=torch.float64) for m in mols])
+    n = n.to("cuda:0")
+    qd = V.compute_q0_batched(grids, n, offs, mols[0].n_cut)
+    E, _ = V.enl_potential_batched(grids, n, offs, qd, table, V.Opts(n_cut=mols[0].n_cut, precision=prec))
+    tol = 1e-6 if prec == 1 else 1e-11
+    worst = 0.0
+    for b, (e, r) in enumerate(zip(E, ref["molecules"])):
+        scale = abs(r["E_pair0"]) + abs(r["E_pairL"]) + abs(r["E_self"])
+        d = max(abs(e[0] - r["E_pair0"]), abs(e[1] - r["E_pairL"]), abs(e[2] - r["E_self"]))
+        worst = max(worst, d / scale)
+        assert d <= tol * scale, (prec, b, e, r)
+        if prec == 0:
+            Er = r["E_pair0"] + r["E_pairL"] + r["E_self"]
+            assert abs(sum(e) - Er) <= 1e-10 * abs(Er), (b, sum(e), Er)
+    say(f"64 molecules precision={prec}: worst per-component error {worst:.2e} of the components' magnitudes")
