@@ -15,7 +15,10 @@ generators); nothing here runs or reads the HIP library.  The values:
     E_self, and E_pairL as twice the sum over one of each image pair (m, -m)
     (the two terms of each pair are equal), one image shift per step;
   * the 64 synthetic molecules of the batch workload, each in full: E_pair0,
-    E_self and the kept count.
+    E_self and the kept count;
+  * the Xe-like slab on the hexagonal cell (skew cell, r <= 30 bohr): E_pair0
+    (the home cell's pairs inside the cut) and E_self; its 80 image cells are
+    left out (about five hours of oracle time).
 
 The run takes hours on a few cores (the slab's image sum is ~4e12 pair
 evaluations), so every finished step is written at once and a rerun resumes
@@ -167,6 +170,22 @@ def main():
                                       kept=int(res.q0["keep"].sum()), seconds=time.time() - t))
         _save(doc)
         print("molecule", b, bent["molecules"][-1], flush=True)
+
+    # --- the hexagonal-cell slab: home cell and on-site term ---
+    key = "xe_hex_slab_home"
+    if key not in wls:
+        wl = W.xe_hex_slab()
+        g = O.Grid(wl.n, wl.h, wl.periodic, cell=wl.cell)
+        t = time.time()
+        qd = O.compute_q0(g, wl.rho, wl.n_cut)
+        idx, ix, iy, iz = O._points(g, qd["keep"])
+        nS, qS = wl.rho.reshape(-1)[idx], qd["q0"][idx]
+        S0, _, _ = O.pair_rows(g, ix, iy, iz, nS, qS, tab, tp, (0, 0, 0), wl.r_cut)
+        e0 = 0.5 * g.dV * g.dV * float(np.sum(nS * S0))
+        wls[key] = dict(E_pair0=e0, E_self=_self_energy(g, nS, qS, tab, tp), kept=int(len(nS)), r_cut=wl.r_cut,
+                        seconds=time.time() - t, host=_host())
+        _save(doc)
+        print(key, wls[key], flush=True)
 
 
 if __name__ == "__main__":

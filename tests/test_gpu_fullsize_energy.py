@@ -153,3 +153,30 @@ def test_molecule_batch_energies_vs_oracle(V, gold, table, prec):
             Er = r["E_pair0"] + r["E_pairL"] + r["E_self"]
             assert abs(sum(e) - Er) <= 1e-10 * abs(Er), (b, sum(e), Er)
     say(f"64 molecules precision={prec}: worst per-component error {worst:.2e} of the components' magnitudes")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_hex_slab_home_cell_vs_oracle(V, gold, table, prec):
+    """The Xe-like slab on the hexagonal (skew) cell of the paper's sample
+    run, images |m|, |p| <= 4 and r <= 30 bohr: E_pair0 (the home cell's pairs
+    inside the cut) and E_self against the oracle's (its image sum is not
+    stored), relative to |E_pair0| + |E_self|: FP32C 1e-6, FP64 1e-11."""
+    import torch
+
+    ref = gold["workloads"].get("xe_hex_slab_home")
+    if ref is None:
+        pytest.skip("the oracle's hexagonal-slab energies are not stored yet")
+    wl = W.xe_hex_slab()
+    assert wl.r_cut == ref["r_cut"]
+    g = V.Grid(wl.n, wl.h, wl.periodic, cell=wl.cell)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    E = V.enl_energy(g, n, qd["q0"], table,
+                     V.Opts(n_cut=wl.n_cut, r_cut=wl.r_cut, image_max=wl.image_max, precision=prec))
+    assert V.last_stats()["retained"] == ref["kept"]
+    scale = abs(ref["E_pair0"]) + abs(ref["E_self"])
+    tol = 1e-6 if prec == 1 else 1e-11
+    d0, ds = abs(E[0] - ref["E_pair0"]) / scale, abs(E[2] - ref["E_self"]) / scale
+    say(f"hex slab precision={prec}: E_pair0 {E[0]:.12e} (oracle {ref['E_pair0']:.12e}), "
+        f"errors {d0:.1e} {ds:.1e}; E_pairL {E[1]:.6e}")
+    assert d0 <= tol and ds <= tol
