@@ -18,7 +18,10 @@ generators); nothing here runs or reads the HIP library.  The values:
     E_self and the kept count;
   * the Xe-like slab on the hexagonal cell (skew cell, r <= 30 bohr): E_pair0
     (the home cell's pairs inside the cut) and E_self; its 80 image cells are
-    left out (about five hours of oracle time).
+    left out (about five hours of oracle time);
+  * the Xe-like slab's far image shell (the large-D asymptote over the cells
+    beyond |m|, |p| <= 2 up to 32, no cut): its energy E_far, the part of
+    E_pairL that the shell adds.
 
 The run takes hours on a few cores (the slab's image sum is ~4e12 pair
 evaluations), so every finished step is written at once and a rerun resumes
@@ -184,6 +187,19 @@ def main():
         e0 = 0.5 * g.dV * g.dV * float(np.sum(nS * S0))
         wls[key] = dict(E_pair0=e0, E_self=_self_energy(g, nS, qS, tab, tp), kept=int(len(nS)), r_cut=wl.r_cut,
                         seconds=time.time() - t, host=_host())
+        _save(doc)
+        print(key, wls[key], flush=True)
+
+    # --- the slab's far image shell ---
+    key = "xe_slab_far_shell"
+    if key not in wls:
+        wl = W.xe_slab()
+        near, far = (2, 2, 0), (32, 32, 0)
+        g, ix, iy, iz, nS, qS = _points(wl)
+        t = time.time()
+        F0, _ = O.far_rows(g, ix, iy, iz, nS, qS, near, far)
+        wls[key] = dict(E_far=0.5 * g.dV * g.dV * float(np.sum(nS * F0)), image_max=list(near), far_max=list(far),
+                        kept=int(len(nS)), seconds=time.time() - t, host=_host())
         _save(doc)
         print(key, wls[key], flush=True)
 

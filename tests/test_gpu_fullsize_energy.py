@@ -180,3 +180,30 @@ def test_hex_slab_home_cell_vs_oracle(V, gold, table, prec):
     say(f"hex slab precision={prec}: E_pair0 {E[0]:.12e} (oracle {ref['E_pair0']:.12e}), "
         f"errors {d0:.1e} {ds:.1e}; E_pairL {E[1]:.6e}")
     assert d0 <= tol and ds <= tol
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_slab_far_shell_vs_oracle(V, gold, table, prec):
+    """The Xe-like slab's far image shell (the kernel's large-D asymptote over
+    the cells beyond |m|, |p| <= 2 up to 32, no cut) at full size: E_pairL
+    with the shell minus E_pairL without it (the near sums are the same
+    launch shapes and cancel bitwise) against the oracle's E_far: FP32C 1e-6
+    (the FP32 records' a and n), FP64 1e-11."""
+    import torch
+
+    ref = gold["workloads"].get("xe_slab_far_shell")
+    if ref is None:
+        pytest.skip("the oracle's far-shell energy is not stored yet")
+    wl = W.xe_slab()
+    g = V.Grid(wl.n, wl.h, wl.periodic)
+    n = torch.tensor(wl.rho.reshape(-1), dtype=torch.float64, device="cuda:0")
+    qd = V.compute_q0(g, n, wl.n_cut)
+    near = tuple(ref["image_max"])
+    E1 = V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, image_max=near, precision=prec))
+    E2 = V.enl_energy(g, n, qd["q0"], table, V.Opts(n_cut=wl.n_cut, image_max=near, far_max=tuple(ref["far_max"]),
+                                                   precision=prec))
+    assert E1[0] == E2[0] and E1[2] == E2[2]
+    Efar = E2[1] - E1[1]
+    rel = abs(Efar - ref["E_far"]) / abs(ref["E_far"])
+    say(f"far shell precision={prec}: E_far {Efar:.12e} (oracle {ref['E_far']:.12e}), rel {rel:.1e}")
+    assert rel <= (1e-6 if prec == 1 else 1e-11)
