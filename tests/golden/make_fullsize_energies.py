@@ -21,7 +21,9 @@ generators); nothing here runs or reads the HIP library.  The values:
     left out (about five hours of oracle time);
   * the Xe-like slab's far image shell (the large-D asymptote over the cells
     beyond |m|, |p| <= 2 up to 32, no cut): its energy E_far, the part of
-    E_pairL that the shell adds.
+    E_pairL that the shell adds;
+  * the rest of the Kr2-like scan, energies only: the dimers at R = 6, 8, 10
+    and 14 bohr, then their atoms alone (about 20 minutes per dimer).
 
 The run takes hours on a few cores (the slab's image sum is ~4e12 pair
 evaluations), so every finished step is written at once and a rerun resumes
@@ -202,6 +204,21 @@ def main():
                         kept=int(len(nS)), seconds=time.time() - t, host=_host())
         _save(doc)
         print(key, wls[key], flush=True)
+
+    # --- the rest of the scan: dimers first, then their atoms ---
+    for which in ("both", "A", "B"):
+        for R in (6.0, 8.0, 10.0, 14.0):
+            key = "kr_dimer_R%g_%s" % (R, which)
+            if key in wls:
+                continue
+            wl = W.kr_dimer(R, which=which)
+            g = O.Grid(wl.n, wl.h, wl.periodic)
+            t = time.time()
+            res = O.evaluate(g, wl.rho, tab, tp, wl.n_cut)
+            wls[key] = dict(E_pair0=res.E_pair0, E_pairL=res.E_pairL, E_self=res.E_self,
+                            kept=int(res.q0["keep"].sum()), seconds=time.time() - t, host=_host())
+            _save(doc)
+            print(key, wls[key], flush=True)
 
 
 if __name__ == "__main__":

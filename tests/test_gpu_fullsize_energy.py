@@ -207,3 +207,44 @@ def test_slab_far_shell_vs_oracle(V, gold, table, prec):
     rel = abs(Efar - ref["E_far"]) / abs(ref["E_far"])
     say(f"far shell precision={prec}: E_far {Efar:.12e} (oracle {ref['E_far']:.12e}), rel {rel:.1e}")
     assert rel <= (1e-6 if prec == 1 else 1e-11)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_kr_scan_batched_vs_oracle(V, gold, table, prec):
+    """The Kr2-like scan as the benchmark evaluates it, its 15 densities (the
+    five dimers and their atoms alone) in one batched call, against every
+    density whose oracle energies are stored, per component over |E|:
+    FP32C 1e-6, FP64 1e-11; and E(R) - E(A) - E(B) wherever all three are."""
+    import torch
+
+    wls_gold = gold["workloads"]
+    dens, keys = [], []
+    for R in W.KR_SEPARATIONS:
+        for which in ("both", "A", "B"):
+            dens.append(W.kr_dimer(R, which=which))
+            keys.append("kr_dimer_R%g_%s" % (R, which))
+    stored = [k for k in keys if k in wls_gold]
+    if len(stored) <= 3:
+        pytest.skip("only the R = 7 densities are stored (tested on their own)")
+    grids = [V.Grid(w.n, w.h, w.periodic) for w in dens]
+    n, offs = V.pack_batch(grids, [torch.tensor(w.rho.reshape(-1), dtype=torch.float64) for w in dens])
+    n = n.to("cuda:0")
+    qd = V.compute_q0_batched(grids, n, offs, dens[0].n_cut)
+    E, _ = V.enl_potential_batched(grids, n, offs, qd, table, V.Opts(n_cut=dens[0].n_cut, precision=prec))
+    tol = TOL[prec][0]
+    for e, k in zip(E, keys):
+        if k not in wls_gold:
+            continue
+        r = wls_gold[k]
+        Er = r["E_pair0"] + r["E_pairL"] + r["E_self"]
+        d = max(abs(e[0] - r["E_pair0"]), abs(e[1] - r["E_pairL"]), abs(e[2] - r["E_self"])) / abs(Er)
+        assert d <= tol, (prec, k, e, r)
+    for t, R in enumerate(W.KR_SEPARATIONS):
+        ks = ["kr_dimer_R%g_%s" % (R, w) for w in ("both", "A", "B")]
+        if all(k in wls_gold for k in ks):
+            ref = [sum(wls_gold[k][c] for c in ("E_pair0", "E_pairL", "E_self")) for k in ks]
+            got = [sum(E[3 * t + j]) for j in range(3)]
+            dref, dgot = ref[0] - ref[1] - ref[2], got[0] - got[1] - got[2]
+            say(f"R = {R:g} precision={prec}: E(R) - E(inf) {dgot:.10e} (oracle {dref:.10e})")
+            assert abs(dgot - dref) <= tol * abs(ref[0])
+    say(f"scan precision={prec}: {len(stored)} of 15 densities against the oracle")
