@@ -881,6 +881,108 @@ __device__ __forceinline__ void ring64(const PairK<R> &kc, const R *tab, const R
     }
 }
 
+// One image shift of a pair in ring64_img: the shift-independent parts (s,
+// the sigma cell l, its fraction fS, w = u / s^2) come in; r, t_D and the D
+// cell are the shift's own.  NEAR / GLOB as in pair_eval; otherwise each lane
+// reads its own source (LDS rows, global rows or the asymptote).
+template <bool ADJ, bool NEAR, bool GLOB>
+__device__ __forceinline__ void img_eval(const PairK<float> &k, const float *tab, float m, float s, float w, int l,
+                                         float fS, int lg, float fSg, float ai, float ej, float ei, float &phi,
+                                         float &dqi, float &dqj)
+{
+    constexpr int S = 65, nS = 64;  // n_sigma = 64: LDS row stride n_sigma + 1
+    const float r = dsqrt(m);
+    const float tD = s * r;
+    const int kk = (int)tD;
+    const float fD = dfract(tD);
+    if (NEAR) {
+        const float *t = tab + (__umul24((unsigned)kk, (unsigned)S) + (unsigned)l);
+        bilinear<float, ADJ, true>(t[0], t[1], t[S], t[S + 1], fD, fS, r, w, 1.0f, 1.0f, ei, ej, phi, dqi, dqj);
+    } else if (GLOB) {
+        const float4 c = k.quad[(uint32_t)(kk * (nS - 1) + lg)];
+        bilinear<float, ADJ, true>(c.x, c.y, c.z, c.w, fD, fSg, r, w, 1.0f, 1.0f, ei, ej, phi, dqi, dqj);
+    } else {
+        if (tD < k.tDlds) {
+            const float *t = tab + (__umul24((unsigned)kk, (unsigned)S) + (unsigned)l);
+            bilinear<float, ADJ, true>(t[0], t[1], t[S], t[S + 1], fD, fS, r, w, 1.0f, 1.0f, ei, ej, phi, dqi, dqj);
+        } else if (tD < k.tDmax) {
+            const float4 c = k.quad[(uint32_t)(kk * (nS - 1) + lg)];
+            bilinear<float, ADJ, true>(c.x, c.y, c.z, c.w, fD, fSg, r, w, 1.0f, 1.0f, ei, ej, phi, dqi, dqj);
+        } else {
+            asymptote<float, ADJ, true>(k, m, ai, ej * k.rc4, phi, dqi, dqj);
+        }
+    }
+}
+
+// kImgGroup image shifts of one j tile in one 64-step ring (FP32, n_sigma =
+// 64, square grids, shifts in x and y only, none of them the home cell).
+// Per step and pair, what does not depend on the shift is formed once:
+// x_i - x_j as an exact f16 pair, its squared length plus the z term (Q0),
+// s = a_i + a_j, 1/s, u, the sigma cell and w = u / s^2; per shift L the
+// squared distance is Q0 + |L|^2 - 2 L . (x_i - x_j), one add and one f16
+// dot product (L and x_i - x_j are exact integers in f16).  ml holds
+// (-2 L_x, -2 L_y) as f16, cl |L|^2.  MASK, NEAR and GLOB hold for every
+// shift of the group.
+constexpr int kImgGroup = 4;
+template <bool ADJ, bool MASK, int IPL, bool NEAR, bool GLOB>
+__device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *tab, float rcm,
+                                           const RecF (&Ir)[IPL], const float (&ai)[IPL], const float (&ci)[IPL],
+                                           const float (&ni)[IPL], float xj, float yj, float zj, float aj, float nj,
+                                           const half2v (&ml)[kImgGroup], const float (&cl)[kImgGroup],
+                                           float (&acc)[IPL], float (&accq)[IPL], float &accj, float &accqj)
+{
+    half2v xyi[IPL];
+    float ei[IPL];
+#pragma unroll
+    for (int p = 0; p < IPL; ++p) {
+        xyi[p] = half2v{(_Float16)Ir[p].x, (_Float16)Ir[p].y};
+        ei[p] = kc.c4 * ai[p];
+    }
+    half2v xyj = half2v{(_Float16)xj, (_Float16)yj};
+    float ej = kc.c4 * aj;  // the j point as 4 csig a_j (see pair_eval)
+    const float wz = kc.wz;
+    for (int st = 0; st < 64; ++st) {
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            const half2v dxy = xyi[p] - xyj;
+            const float dz = Ir[p].z - zj;
+            const float q0 = fmaf(wz * dz, dz, __builtin_amdgcn_fdot2(dxy, dxy, 0.0f, false));
+            const float s = fmaf(ej, kc.rc4, ai[p]);
+            const float inv = drcp(s);
+            const float u = fmaf(ci[p], inv, -kc.csig);
+            const float ts = u * u;
+            const int l = (int)ts;
+            const float fS = dfract(ts);
+            const int lg = min(l, 64 - 2);  // the global rows have no column beyond n_sigma - 1
+            const float fSg = ts - (float)lg;
+            const float w = (u * inv) * inv;
+#pragma unroll
+            for (int g = 0; g < kImgGroup; ++g) {
+                const float m = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                float ph, dqi = 0.0f, dqj = 0.0f;
+                img_eval<ADJ, NEAR, GLOB>(kc, tab, m, s, w, l, fS, lg, fSg, ai[p], ej, ei[p], ph, dqi, dqj);
+                float wjp = nj, wip = ni[p];
+                if (MASK) {
+                    wjp = (m <= rcm) ? nj : 0.0f;
+                    wip = (m <= rcm) ? ni[p] : 0.0f;
+                }
+                acc[p] = fmaf(wjp, ph, acc[p]);
+                accj = fmaf(wip, ph, accj);
+                if (ADJ) {
+                    accq[p] = fmaf(wjp, dqi, accq[p]);
+                    accqj = fmaf(wip, dqj, accqj);
+                }
+            }
+        }
+        xyj = wrot(xyj);
+        zj = wrot(zj);
+        ej = wrot(ej);
+        nj = wrot(nj);
+        accj = wrot(accj);
+        if (ADJ) accqj = wrot(accqj);
+    }
+}
+
 // Wavefront-wide min / max (every lane gets the result; all 64 lanes active).
 // FP32: rotations within each row of 16 lanes (DPP row_ror 8, 4, 2, 1) leave
 // every lane with its row's result, then the four rows are read out, all
@@ -1218,64 +1320,193 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 // j-side sums of the tile over the image shifts, carried in
                 // FP64 after every 64-step ring (as the i side)
                 double jSc = 0.0, jSL = 0.0, jSq = 0.0;
-                for (int L = 0; L < nimg; ++L) {
-                    R lx = 0, ly = 0, lz = 0;
-                    bool home = true, masked = prune;  // no cut: every tile unmasked
-                    bool near = false, glob = false;
-                    if (IMG) {
-                        lx = (R)(imgs[4 * L + 0] * sg.nx);
-                        ly = (R)(imgs[4 * L + 1] * sg.ny);
-                        lz = (R)(imgs[4 * L + 2] * sg.nz);
-                        home = (L == A.home);
-                    }
-                    if (prune || NEARABLE) {
-                        // r_i - r_j - L: the j box shifted by +L against the i box
-                        R dmin2, dmax2, bx, by, bz;
-                        box_pos<R, GEO>(kc, lx, ly, lz, bx, by, bz);
-                        box_dist2<R, GEO == kSkew>(kc, ib, jb6, bx, by, bz, dmin2, dmax2);
-                        if (prune) {
-                            if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
-                            masked = dmax2 > rcm;
-                        }
-                        if (NEARABLE) {
-                            const R hi = (aimax + ajmax) * sqrt(dmax2) * (R)(1.0 + 1.0 / 1024.0);
-                            near = hi < kc.tDlds;
-                            glob = GLOBABLE && hi < kc.tDmax &&
-                                   (aimin + ajmin) * sqrt(dmin2) * (R)(1.0 - 1.0 / 1024.0) >= kc.tDlds;
-                        }
-                    }
-                    R sx[IPL], sy[IPL], sz[IPL], acc[IPL], accq[IPL];
-#pragma unroll
-                    for (int p = 0; p < IPL; ++p) {
-                        sx[p] = Ir[p].x - lx;
-                        sy[p] = Ir[p].y - ly;
-                        sz[p] = Ir[p].z - lz;
-                        acc[p] = accq[p] = 0;
-                    }
-                    R accj = 0, accqj = 0;
+                // FP32 n_sigma = 64 image kernels on square grids: the image
+                // shifts of the first 64 (those in x and y only, not the home
+                // cell) are sorted by ring class (masked or not; NEAR, GLOB or
+                // per-lane source) and run kImgGroup at a time (ring64_img);
+                // the rest of a class, and every other shift, one at a time
+                constexpr bool GRP = IMG && GEO == kSquare && sizeof(R) == 4 && !KAHAN && NSIG == 64;
+                if constexpr (GRP) {
                     const R nj0 = jv ? Jr.n : (R)0;
+                    // one 64-step ring of the tile against one shift, carried into
+                    // the FP64 sums of the home cell or of the images
+                    auto one_ring = [&](R lx, R ly, R lz, bool home, bool masked, bool near, bool glob) {
+                        R sx[IPL], sy[IPL], sz[IPL], acc[IPL], accq[IPL];
+#pragma unroll
+                        for (int p = 0; p < IPL; ++p) {
+                            sx[p] = Ir[p].x - lx;
+                            sy[p] = Ir[p].y - ly;
+                            sz[p] = Ir[p].z - lz;
+                            acc[p] = accq[p] = 0;
+                        }
+                        R accj = 0, accqj = 0;
 #define RING(MSK, NR, GL)                                                                                          \
-    ring64<R, ADJ, MSK, KAHAN, NSIG, GEO, IPL, IMG, NR, GL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x, Jr.y, Jr.z, \
-                                                         Jr.w, Jr.a, nj0, acc, accq, accj, accqj)
-                    if (masked) {
-                        if (NEARABLE && near) RING(true, NEARABLE, false);
-                        else if (GLOBABLE && glob) RING(true, false, GLOBABLE);
-                        else RING(true, false, false);
-                    } else {
-                        if (NEARABLE && near) RING(false, NEARABLE, false);
-                        else if (GLOBABLE && glob) RING(false, false, GLOBABLE);
-                        else RING(false, false, false);
-                    }
+        ring64<R, ADJ, MSK, KAHAN, NSIG, GEO, IPL, IMG, NR, GL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x, Jr.y, Jr.z, \
+                                                             Jr.w, Jr.a, nj0, acc, accq, accj, accqj)
+                        if (masked) {
+                            if (NEARABLE && near) RING(true, NEARABLE, false);
+                            else if (GLOBABLE && glob) RING(true, false, GLOBABLE);
+                            else RING(true, false, false);
+                        } else {
+                            if (NEARABLE && near) RING(false, NEARABLE, false);
+                            else if (GLOBABLE && glob) RING(false, false, GLOBABLE);
+                            else RING(false, false, false);
+                        }
 #undef RING
 #pragma unroll
-                    for (int p = 0; p < IPL; ++p) {
-                        if (home) Sc[p] += (double)acc[p];
-                        else SL[p] += (double)acc[p];
-                        if (ADJ) Sq[p] += (double)accq[p];
+                        for (int p = 0; p < IPL; ++p) {
+                            if (home) Sc[p] += (double)acc[p];
+                            else SL[p] += (double)acc[p];
+                            if (ADJ) Sq[p] += (double)accq[p];
+                        }
+                        if (home) jSc += (double)accj;
+                        else jSL += (double)accj;
+                        if (ADJ) jSq += (double)accqj;
+                    };
+                    uint64_t gm[6] = {0, 0, 0, 0, 0, 0};  // class 3 masked + (0 NEAR, 1 GLOB, 2 per lane)
+                    for (int L = 0; L < nimg; ++L) {
+                        R lx = 0, ly = 0, lz = 0;
+                        bool home = true, masked = prune;  // no cut: every tile unmasked
+                        bool near = false, glob = false;
+                        if (IMG) {
+                            lx = (R)(imgs[4 * L + 0] * sg.nx);
+                            ly = (R)(imgs[4 * L + 1] * sg.ny);
+                            lz = (R)(imgs[4 * L + 2] * sg.nz);
+                            home = (L == A.home);
+                        }
+                        if (prune || NEARABLE) {
+                            // r_i - r_j - L: the j box shifted by +L against the i box
+                            R dmin2, dmax2, bx, by, bz;
+                            box_pos<R, GEO>(kc, lx, ly, lz, bx, by, bz);
+                            box_dist2<R, GEO == kSkew>(kc, ib, jb6, bx, by, bz, dmin2, dmax2);
+                            if (prune) {
+                                if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
+                                masked = dmax2 > rcm;
+                            }
+                            if (NEARABLE) {
+                                const R hi = (aimax + ajmax) * sqrt(dmax2) * (R)(1.0 + 1.0 / 1024.0);
+                                near = hi < kc.tDlds;
+                                glob = GLOBABLE && hi < kc.tDmax &&
+                                       (aimin + ajmin) * sqrt(dmin2) * (R)(1.0 - 1.0 / 1024.0) >= kc.tDlds;
+                            }
+                        }
+                        if (GRP && !home && lz == (R)0 && L < 64) {
+                            const int cls = (masked ? 3 : 0) + (near ? 0 : glob ? 1 : 2);
+#pragma unroll
+                            for (int c6 = 0; c6 < 6; ++c6)  // constant indices: the masks stay in registers
+                                if (c6 == cls) gm[c6] |= 1ull << L;
+                            continue;
+                        }
+                        one_ring(lx, ly, lz, home, masked, near, glob);
                     }
-                    if (home) jSc += (double)accj;
-                    else jSL += (double)accj;
-                    if (ADJ) jSq += (double)accqj;
+                    if constexpr (GRP) {
+#pragma unroll
+                        for (int cl6 = 0; cl6 < 6; ++cl6) {
+                            uint64_t mk = gm[cl6];
+                            while (__builtin_popcountll(mk) >= kImgGroup) {
+                                half2v ml[kImgGroup];
+                                float cL[kImgGroup];
+#pragma unroll
+                                for (int g = 0; g < kImgGroup; ++g) {
+                                    const int L = __builtin_ctzll(mk);
+                                    mk &= mk - 1;
+                                    const float lx = (float)(imgs[4 * L + 0] * sg.nx);
+                                    const float ly = (float)(imgs[4 * L + 1] * sg.ny);
+                                    ml[g] = half2v{(_Float16)(-2.0f * lx), (_Float16)(-2.0f * ly)};
+                                    cL[g] = lx * lx + ly * ly;
+                                }
+                                R acc[IPL], accq[IPL];
+#pragma unroll
+                                for (int p = 0; p < IPL; ++p) acc[p] = accq[p] = 0;
+                                R accj = 0, accqj = 0;
+#define RINGI(MSK, NR, GL)                                                                                   \
+        ring64_img<ADJ, MSK, IPL, NR, GL>(kc, tab, rcm, Ir, ai, ci, ni, Jr.x, Jr.y, Jr.z, Jr.a, nj0, ml, cL, acc, accq, \
+                                          accj, accqj)
+                                switch (cl6) {
+                                case 0: RINGI(false, true, false); break;
+                                case 1: RINGI(false, false, true); break;
+                                case 2: RINGI(false, false, false); break;
+                                case 3: RINGI(true, true, false); break;
+                                case 4: RINGI(true, false, true); break;
+                                default: RINGI(true, false, false); break;
+                                }
+#undef RINGI
+#pragma unroll
+                                for (int p = 0; p < IPL; ++p) {
+                                    SL[p] += (double)acc[p];
+                                    if (ADJ) Sq[p] += (double)accq[p];
+                                }
+                                jSL += (double)accj;
+                                if (ADJ) jSq += (double)accqj;
+                            }
+                            while (mk) {
+                                const int L = __builtin_ctzll(mk);
+                                mk &= mk - 1;
+                                one_ring((R)(imgs[4 * L + 0] * sg.nx), (R)(imgs[4 * L + 1] * sg.ny), (R)0, false,
+                                         cl6 >= 3, cl6 % 3 == 0, cl6 % 3 == 1);
+                            }
+                        }
+                    }
+                } else {
+                    for (int L = 0; L < nimg; ++L) {
+                        R lx = 0, ly = 0, lz = 0;
+                        bool home = true, masked = prune;  // no cut: every tile unmasked
+                        bool near = false, glob = false;
+                        if (IMG) {
+                            lx = (R)(imgs[4 * L + 0] * sg.nx);
+                            ly = (R)(imgs[4 * L + 1] * sg.ny);
+                            lz = (R)(imgs[4 * L + 2] * sg.nz);
+                            home = (L == A.home);
+                        }
+                        if (prune || NEARABLE) {
+                            // r_i - r_j - L: the j box shifted by +L against the i box
+                            R dmin2, dmax2, bx, by, bz;
+                            box_pos<R, GEO>(kc, lx, ly, lz, bx, by, bz);
+                            box_dist2<R, GEO == kSkew>(kc, ib, jb6, bx, by, bz, dmin2, dmax2);
+                            if (prune) {
+                                if (dmin2 > rcm) continue;  // the whole tile is beyond the cut
+                                masked = dmax2 > rcm;
+                            }
+                            if (NEARABLE) {
+                                const R hi = (aimax + ajmax) * sqrt(dmax2) * (R)(1.0 + 1.0 / 1024.0);
+                                near = hi < kc.tDlds;
+                                glob = GLOBABLE && hi < kc.tDmax &&
+                                       (aimin + ajmin) * sqrt(dmin2) * (R)(1.0 - 1.0 / 1024.0) >= kc.tDlds;
+                            }
+                        }
+                        R sx[IPL], sy[IPL], sz[IPL], acc[IPL], accq[IPL];
+#pragma unroll
+                        for (int p = 0; p < IPL; ++p) {
+                            sx[p] = Ir[p].x - lx;
+                            sy[p] = Ir[p].y - ly;
+                            sz[p] = Ir[p].z - lz;
+                            acc[p] = accq[p] = 0;
+                        }
+                        R accj = 0, accqj = 0;
+                        const R nj0 = jv ? Jr.n : (R)0;
+#define RING(MSK, NR, GL)                                                                                          \
+        ring64<R, ADJ, MSK, KAHAN, NSIG, GEO, IPL, IMG, NR, GL>(kc, tab, tabg, rcm, sx, sy, sz, ai, ci, ni, Jr.x, Jr.y, Jr.z, \
+                                                             Jr.w, Jr.a, nj0, acc, accq, accj, accqj)
+                        if (masked) {
+                            if (NEARABLE && near) RING(true, NEARABLE, false);
+                            else if (GLOBABLE && glob) RING(true, false, GLOBABLE);
+                            else RING(true, false, false);
+                        } else {
+                            if (NEARABLE && near) RING(false, NEARABLE, false);
+                            else if (GLOBABLE && glob) RING(false, false, GLOBABLE);
+                            else RING(false, false, false);
+                        }
+#undef RING
+#pragma unroll
+                        for (int p = 0; p < IPL; ++p) {
+                            if (home) Sc[p] += (double)acc[p];
+                            else SL[p] += (double)acc[p];
+                            if (ADJ) Sq[p] += (double)accq[p];
+                        }
+                        if (home) jSc += (double)accj;
+                        else jSL += (double)accj;
+                        if (ADJ) jSq += (double)accqj;
+                    }
                 }
                 // j-side sums of the tile: the wavefronts' FP64 partials added
                 // in a fixed order, one accumulator array at a time
