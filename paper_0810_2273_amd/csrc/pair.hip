@@ -956,11 +956,37 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
             const int lg = min(l, 64 - 2);  // the global rows have no column beyond n_sigma - 1
             const float fSg = ts - (float)lg;
             const float w = (u * inv) * inv;
+            // NEAR, GLOB: the four shifts' table cells are read first, then
+            // interpolated, so that their loads are in flight together
+            float mg[kImgGroup], rg[kImgGroup], fDg[kImgGroup];
+            float4 cg[kImgGroup];
+            if (NEAR || GLOB) {
+#pragma unroll
+                for (int g = 0; g < kImgGroup; ++g) {
+                    mg[g] = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                    rg[g] = dsqrt(mg[g]);
+                    const float tD = s * rg[g];
+                    const int kk = (int)tD;
+                    fDg[g] = dfract(tD);
+                    if (NEAR) {
+                        const float *t = tab + (__umul24((unsigned)kk, 65u) + (unsigned)l);
+                        cg[g] = make_float4(t[0], t[1], t[65], t[66]);
+                    } else {
+                        cg[g] = kc.quad[(uint32_t)(kk * (64 - 1) + lg)];
+                    }
+                }
+            }
 #pragma unroll
             for (int g = 0; g < kImgGroup; ++g) {
-                const float m = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
-                float ph, dqi = 0.0f, dqj = 0.0f;
-                img_eval<ADJ, NEAR, GLOB>(kc, tab, m, s, w, l, fS, lg, fSg, ai[p], ej, ei[p], ph, dqi, dqj);
+                float m, ph, dqi = 0.0f, dqj = 0.0f;
+                if (NEAR || GLOB) {
+                    m = mg[g];
+                    bilinear<float, ADJ, true>(cg[g].x, cg[g].y, cg[g].z, cg[g].w, fDg[g], NEAR ? fS : fSg, rg[g], w,
+                                               1.0f, 1.0f, ei[p], ej, ph, dqi, dqj);
+                } else {
+                    m = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                    img_eval<ADJ, NEAR, GLOB>(kc, tab, m, s, w, l, fS, lg, fSg, ai[p], ej, ei[p], ph, dqi, dqj);
+                }
                 float wjp = nj, wip = ni[p];
                 if (MASK) {
                     wjp = (m <= rcm) ? nj : 0.0f;
