@@ -914,7 +914,7 @@ __device__ __forceinline__ void img_eval(const PairK<float> &k, const float *tab
     }
 }
 
-// kImgGroup image shifts of one j tile in one 64-step ring (FP32, n_sigma =
+// G image shifts of one j tile in one 64-step ring (FP32, n_sigma =
 // 64, square grids, shifts in x and y only, none of them the home cell).
 // Per step and pair, what does not depend on the shift is formed once:
 // x_i - x_j as an exact f16 pair, its squared length plus the z term (Q0),
@@ -922,13 +922,18 @@ __device__ __forceinline__ void img_eval(const PairK<float> &k, const float *tab
 // squared distance is Q0 + |L|^2 - 2 L . (x_i - x_j), one add and one f16
 // dot product (L and x_i - x_j are exact integers in f16).  ml holds
 // (-2 L_x, -2 L_y) as f16, cl |L|^2.  MASK, NEAR and GLOB hold for every
-// shift of the group.
+// shift of the group.  Groups of kImgGroup shifts, then at most one of two
+// per class (larger groups spill).
 constexpr int kImgGroup = 4;
-template <bool ADJ, bool MASK, int IPL, bool NEAR, bool GLOB>
+template <int N>
+struct IntC {
+    static constexpr int value = N;
+};
+template <bool ADJ, bool MASK, int IPL, bool NEAR, bool GLOB, int G>
 __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *tab, float rcm,
                                            const RecF (&Ir)[IPL], const float (&ai)[IPL], const float (&ci)[IPL],
                                            const float (&ni)[IPL], float xj, float yj, float zj, float aj, float nj,
-                                           const half2v (&ml)[kImgGroup], const float (&cl)[kImgGroup],
+                                           const half2v (&ml)[G], const float (&cl)[G],
                                            float (&acc)[IPL], float (&accq)[IPL], float &accj, float &accqj)
 {
     half2v xyi[IPL];
@@ -958,11 +963,11 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
             const float w = (u * inv) * inv;
             // NEAR, GLOB: the four shifts' table cells are read first, then
             // interpolated, so that their loads are in flight together
-            float mg[kImgGroup], rg[kImgGroup], fDg[kImgGroup];
-            float4 cg[kImgGroup];
+            float mg[G], rg[G], fDg[G];
+            float4 cg[G];
             if (NEAR || GLOB) {
 #pragma unroll
-                for (int g = 0; g < kImgGroup; ++g) {
+                for (int g = 0; g < G; ++g) {
                     mg[g] = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
                     rg[g] = dsqrt(mg[g]);
                     const float tD = s * rg[g];
@@ -977,7 +982,7 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
                 }
             }
 #pragma unroll
-            for (int g = 0; g < kImgGroup; ++g) {
+            for (int g = 0; g < G; ++g) {
                 float m, ph, dqi = 0.0f, dqj = 0.0f;
                 if (NEAR || GLOB) {
                     m = mg[g];
@@ -1429,11 +1434,13 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
 #pragma unroll
                         for (int cl6 = 0; cl6 < 6; ++cl6) {
                             uint64_t mk = gm[cl6];
-                            while (__builtin_popcountll(mk) >= kImgGroup) {
-                                half2v ml[kImgGroup];
-                                float cL[kImgGroup];
+                            // the next Gc::value shifts of mk as one ring of class cl6
+                            auto group_ring = [&](auto Gc) {
+                                constexpr int G = decltype(Gc)::value;
+                                half2v ml[G];
+                                float cL[G];
 #pragma unroll
-                                for (int g = 0; g < kImgGroup; ++g) {
+                                for (int g = 0; g < G; ++g) {
                                     const int L = __builtin_ctzll(mk);
                                     mk &= mk - 1;
                                     const float lx = (float)(imgs[4 * L + 0] * sg.nx);
@@ -1445,9 +1452,9 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
 #pragma unroll
                                 for (int p = 0; p < IPL; ++p) acc[p] = accq[p] = 0;
                                 R accj = 0, accqj = 0;
-#define RINGI(MSK, NR, GL)                                                                                   \
-        ring64_img<ADJ, MSK, IPL, NR, GL>(kc, tab, rcm, Ir, ai, ci, ni, Jr.x, Jr.y, Jr.z, Jr.a, nj0, ml, cL, acc, accq, \
-                                          accj, accqj)
+#define RINGI(MSK, NR, GL)                                                                                          \
+    ring64_img<ADJ, MSK, IPL, NR, GL, G>(kc, tab, rcm, Ir, ai, ci, ni, Jr.x, Jr.y, Jr.z, Jr.a, nj0, ml, cL, acc, accq, \
+                                         accj, accqj)
                                 switch (cl6) {
                                 case 0: RINGI(false, true, false); break;
                                 case 1: RINGI(false, false, true); break;
@@ -1464,7 +1471,9 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                                 }
                                 jSL += (double)accj;
                                 if (ADJ) jSq += (double)accqj;
-                            }
+                            };
+                            while (__builtin_popcountll(mk) >= kImgGroup) group_ring(IntC<kImgGroup>{});
+                            if (__builtin_popcountll(mk) >= 2) group_ring(IntC<2>{});
                             while (mk) {
                                 const int L = __builtin_ctzll(mk);
                                 mk &= mk - 1;
