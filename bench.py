@@ -46,8 +46,8 @@ PEAK_FP32_TFLOPS = 157.3
 PROFILE_COUNTERS = {
     "kr": {"source": "profiles/pair_kernel_kr_scan96_fp32c.md", "executed_tflops": 43.6,
            "valu_instructions_per_issue_slot": 1.06, "lane_instructions_per_unordered_pair": 37.6},
-    "slab": {"source": "profiles/pair_kernel_xe_slab_literal_fp32c.md", "executed_tflops": 31.2,
-             "valu_instructions_per_issue_slot": 0.75, "lane_instructions_per_in_cut_unordered_pair": 39.8},
+    "slab": {"source": "profiles/pair_kernel_xe_slab_literal_fp32c.md", "executed_tflops": 31.9,
+             "valu_instructions_per_issue_slot": 0.76, "lane_instructions_per_in_cut_unordered_pair": 39.1},
 }
 # Far image shell (FP64): algorithmic FLOP per ordered pair of the row pass
 # (a_i^2 a_j^2 (a_i^2 + a_j^2), its reciprocal, the weighted sum and the
@@ -60,7 +60,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per pair-kernel launch, from rocprofv3 FETCH_SIZE (x 2.0, the
 # factor a plain 512 MiB copy needs) + WRITE_SIZE of the current kernel
 # (profiles/); a workload without a profile of the current kernel has none.
-TRAFFIC_BYTES = {"kr": (5308970.0 * 2.0 + 8971550.0) * 1024, "slab": (414114.0 * 2.0 + 891907.0) * 1024}
+TRAFFIC_BYTES = {"kr": (5308970.0 * 2.0 + 8971550.0) * 1024, "slab": (411084.0 * 2.0 + 891907.0) * 1024}
 # The metric's accuracy gate: FP32C against the FP64 form (and against the
 # oracle's full-size energies where they are stored).
 GATE_DE_REL = 1e-6
