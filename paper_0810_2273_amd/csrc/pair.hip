@@ -929,13 +929,21 @@ template <int N>
 struct IntC {
     static constexpr int value = N;
 };
-template <bool ADJ, bool MASK, int IPL, bool NEAR, bool GLOB, int G>
+//
+// Skew cells (GEO == kSkew): the shift L = (L_x, L_y, 0) in grid steps; the
+// components of d - L are formed exactly (integers) and the metric is
+// evaluated on them with the z terms of the pair hoisted (wz dz^2, m02 dz,
+// m12 dz), since expanding |d - L|^2 about |d|^2 would cancel for pairs
+// close only across the cell boundary.  lxy holds (L_x, L_y); ml, cl are
+// unused there.
+template <bool ADJ, bool MASK, int IPL, bool NEAR, bool GLOB, int G, int GEO = kSquare>
 __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *tab, float rcm,
                                            const RecF (&Ir)[IPL], const float (&ai)[IPL], const float (&ci)[IPL],
                                            const float (&ni)[IPL], float xj, float yj, float zj, float aj, float nj,
-                                           const half2v (&ml)[G], const float (&cl)[G],
+                                           const half2v (&ml)[G], const float (&cl)[G], const float2 (&lxy)[G],
                                            float (&acc)[IPL], float (&accq)[IPL], float &accj, float &accqj)
 {
+    constexpr bool SKEW = GEO == kSkew;
     half2v xyi[IPL];
     float ei[IPL];
 #pragma unroll
@@ -949,9 +957,20 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
     for (int st = 0; st < 64; ++st) {
 #pragma unroll
         for (int p = 0; p < IPL; ++p) {
-            const half2v dxy = xyi[p] - xyj;
-            const float dz = Ir[p].z - zj;
-            const float q0 = fmaf(wz * dz, dz, __builtin_amdgcn_fdot2(dxy, dxy, 0.0f, false));
+            half2v dxy;
+            float q0 = 0.0f, dx = 0.0f, dy = 0.0f, zA = 0.0f, zx = 0.0f, zy = 0.0f;
+            if constexpr (SKEW) {
+                const float dz = Ir[p].z - zj;
+                dx = Ir[p].x - xj;
+                dy = Ir[p].y - yj;
+                zA = (kc.wz * dz) * dz;
+                zx = kc.m02 * dz;
+                zy = kc.m12 * dz;
+            } else {
+                dxy = xyi[p] - xyj;
+                const float dz = Ir[p].z - zj;
+                q0 = fmaf(wz * dz, dz, __builtin_amdgcn_fdot2(dxy, dxy, 0.0f, false));
+            }
             const float s = fmaf(ej, kc.rc4, ai[p]);
             const float inv = drcp(s);
             const float u = fmaf(ci[p], inv, -kc.csig);
@@ -968,7 +987,12 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
             if (NEAR || GLOB) {
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
-                    mg[g] = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                    if constexpr (SKEW) {
+                        const float ex = dx - lxy[g].x, ey = dy - lxy[g].y;
+                        mg[g] = fmaf(ex, fmaf(kc.m01, ey, ex + zx), fmaf(ey, fmaf(kc.wy, ey, zy), zA));
+                    } else {
+                        mg[g] = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                    }
                     rg[g] = dsqrt(mg[g]);
                     const float tD = s * rg[g];
                     const int kk = (int)tD;
@@ -989,7 +1013,12 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
                     bilinear<float, ADJ, true>(cg[g].x, cg[g].y, cg[g].z, cg[g].w, fDg[g], NEAR ? fS : fSg, rg[g], w,
                                                1.0f, 1.0f, ei[p], ej, ph, dqi, dqj);
                 } else {
-                    m = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                    if constexpr (SKEW) {
+                        const float ex = dx - lxy[g].x, ey = dy - lxy[g].y;
+                        m = fmaf(ex, fmaf(kc.m01, ey, ex + zx), fmaf(ey, fmaf(kc.wy, ey, zy), zA));
+                    } else {
+                        m = __builtin_amdgcn_fdot2(ml[g], dxy, q0 + cl[g], false);
+                    }
                     img_eval<ADJ, NEAR, GLOB>(kc, tab, m, s, w, l, fS, lg, fSg, ai[p], ej, ei[p], ph, dqi, dqj);
                 }
                 float wjp = nj, wip = ni[p];
@@ -1005,7 +1034,12 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
                 }
             }
         }
-        xyj = wrot(xyj);
+        if constexpr (SKEW) {
+            xj = wrot(xj);
+            yj = wrot(yj);
+        } else {
+            xyj = wrot(xyj);
+        }
         zj = wrot(zj);
         ej = wrot(ej);
         nj = wrot(nj);
@@ -1351,12 +1385,13 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                 // j-side sums of the tile over the image shifts, carried in
                 // FP64 after every 64-step ring (as the i side)
                 double jSc = 0.0, jSL = 0.0, jSq = 0.0;
-                // FP32 n_sigma = 64 image kernels on square grids: the image
-                // shifts of the first 64 (those in x and y only, not the home
-                // cell) are sorted by ring class (masked or not; NEAR, GLOB or
-                // per-lane source) and run kImgGroup at a time (ring64_img);
-                // the rest of a class, and every other shift, one at a time
-                constexpr bool GRP = IMG && GEO == kSquare && sizeof(R) == 4 && !KAHAN && NSIG == 64;
+                // FP32 n_sigma = 64 image kernels on square and skew grids: the
+                // image shifts of the first 64 (those in x and y only, not the
+                // home cell) are sorted by ring class (masked or not; NEAR, GLOB
+                // or per-lane source) and run kImgGroup at a time (ring64_img),
+                // two or three left of a class two at a time; the last one of a
+                // class, and every other shift, one at a time
+                constexpr bool GRP = IMG && (GEO == kSquare || GEO == kSkew) && sizeof(R) == 4 && !KAHAN && NSIG == 64;
                 if constexpr (GRP) {
                     const R nj0 = jv ? Jr.n : (R)0;
                     // one 64-step ring of the tile against one shift, carried into
@@ -1439,6 +1474,7 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                                 constexpr int G = decltype(Gc)::value;
                                 half2v ml[G];
                                 float cL[G];
+                                float2 lxy[G];
 #pragma unroll
                                 for (int g = 0; g < G; ++g) {
                                     const int L = __builtin_ctzll(mk);
@@ -1447,14 +1483,15 @@ __global__ __launch_bounds__(TPB) void pair_kernel(PairArgs A, const typename Re
                                     const float ly = (float)(imgs[4 * L + 1] * sg.ny);
                                     ml[g] = half2v{(_Float16)(-2.0f * lx), (_Float16)(-2.0f * ly)};
                                     cL[g] = lx * lx + ly * ly;
+                                    lxy[g] = make_float2(lx, ly);
                                 }
                                 R acc[IPL], accq[IPL];
 #pragma unroll
                                 for (int p = 0; p < IPL; ++p) acc[p] = accq[p] = 0;
                                 R accj = 0, accqj = 0;
 #define RINGI(MSK, NR, GL)                                                                                          \
-    ring64_img<ADJ, MSK, IPL, NR, GL, G>(kc, tab, rcm, Ir, ai, ci, ni, Jr.x, Jr.y, Jr.z, Jr.a, nj0, ml, cL, acc, accq, \
-                                         accj, accqj)
+    ring64_img<ADJ, MSK, IPL, NR, GL, G, GEO>(kc, tab, rcm, Ir, ai, ci, ni, Jr.x, Jr.y, Jr.z, Jr.a, nj0, ml, cL, lxy, \
+                                              acc, accq, accj, accqj)
                                 switch (cl6) {
                                 case 0: RINGI(false, true, false); break;
                                 case 1: RINGI(false, false, true); break;
