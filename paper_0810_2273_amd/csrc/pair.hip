@@ -914,28 +914,30 @@ __device__ __forceinline__ void img_eval(const PairK<float> &k, const float *tab
     }
 }
 
-// G image shifts of one j tile in one 64-step ring (FP32, n_sigma =
-// 64, square grids, shifts in x and y only, none of them the home cell).
-// Per step and pair, what does not depend on the shift is formed once:
-// x_i - x_j as an exact f16 pair, its squared length plus the z term (Q0),
-// s = a_i + a_j, 1/s, u, the sigma cell and w = u / s^2; per shift L the
-// squared distance is Q0 + |L|^2 - 2 L . (x_i - x_j), one add and one f16
-// dot product (L and x_i - x_j are exact integers in f16).  ml holds
-// (-2 L_x, -2 L_y) as f16, cl |L|^2.  MASK, NEAR and GLOB hold for every
-// shift of the group.  Groups of kImgGroup shifts, then at most one of two
-// per class (larger groups spill).
-constexpr int kImgGroup = 4;
+constexpr int kImgGroup = 4;  // shifts per ring (groups of six or eight spill)
 template <int N>
 struct IntC {
     static constexpr int value = N;
 };
+
+// G image shifts of one j tile in one 64-step ring (FP32, n_sigma = 64,
+// square or skew grids, shifts in x and y only, none of them the home cell).
+// Per step and pair, what does not depend on the shift is formed once: s =
+// a_i + a_j, 1/s, u, the sigma cell and w = u / s^2, and the shift-free part
+// of the squared distance.  MASK, NEAR and GLOB hold for every shift of the
+// group.  The caller runs groups of kImgGroup shifts, then at most one group
+// of two per ring class.
 //
-// Skew cells (GEO == kSkew): the shift L = (L_x, L_y, 0) in grid steps; the
-// components of d - L are formed exactly (integers) and the metric is
-// evaluated on them with the z terms of the pair hoisted (wz dz^2, m02 dz,
-// m12 dz), since expanding |d - L|^2 about |d|^2 would cancel for pairs
-// close only across the cell boundary.  lxy holds (L_x, L_y); ml, cl are
-// unused there.
+// Square grids: x_i - x_j is an exact f16 pair and Q0 its squared length
+// plus the z term; per shift L the squared distance is Q0 + |L|^2 - 2 L .
+// (x_i - x_j), one add and one f16 dot product (L and x_i - x_j are exact
+// integers in f16).  ml holds (-2 L_x, -2 L_y) as f16, cl |L|^2.
+//
+// Skew cells: the components of d - L (grid steps) are formed exactly and
+// the metric is evaluated on them with the pair's z terms hoisted (wz dz^2,
+// m02 dz, m12 dz); expanding |d - L|^2 about |d|^2 instead would cancel for
+// pairs close only across the cell boundary.  lxy holds (L_x, L_y); ml and cl
+// are unused there.
 template <bool ADJ, bool MASK, int IPL, bool NEAR, bool GLOB, int G, int GEO = kSquare>
 __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *tab, float rcm,
                                            const RecF (&Ir)[IPL], const float (&ai)[IPL], const float (&ci)[IPL],
@@ -980,7 +982,7 @@ __device__ __forceinline__ void ring64_img(const PairK<float> &kc, const float *
             const int lg = min(l, 64 - 2);  // the global rows have no column beyond n_sigma - 1
             const float fSg = ts - (float)lg;
             const float w = (u * inv) * inv;
-            // NEAR, GLOB: the four shifts' table cells are read first, then
+            // NEAR, GLOB: the group's table cells are read first, then
             // interpolated, so that their loads are in flight together
             float mg[G], rg[G], fDg[G];
             float4 cg[G];
